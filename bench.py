@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark: 3DES-EDE ECB encryption of 1 GiB (134,217,728 blocks) resident
+in HBM on one MI355X, through the library's C ABI.
+
+One step = key schedule of the 3-key bundle (host) + one fused 48-round
+encryption launch over the whole buffer.  W untimed warm-up steps, then K
+timed steps between device synchronisations; every launch is also bracketed
+by HIP events on the stream it runs on, which gives the kernel's own average
+duration for the roofline figure.  The oracle is timed on the host cores on
+a bounded sample of the same input (cpu_baseline).
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GIB = 1 << 30
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kernel", default="bitslice", choices=["bitslice", "spbox"])
+    ap.add_argument("--nbytes", type=int, default=GIB, help="payload bytes (default 1 GiB)")
+    ap.add_argument("--input", default="uniform", choices=["uniform", "zero", "pattern"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the oracle sample (0 disables)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain device copies of the same size (for PMC scaling)")
+    return ap.parse_args()
+
+
+def cpu_baseline(key, host, target_s):
+    import numpy as np
+
+    import oracle
+    threads = oracle.set_threads(0)
+    # calibrate on a small slice, then size the sample for ~target_s
+    probe = host[: 8 * 16384]
+    t0 = time.perf_counter()
+    oracle.tdes_ecb(key, probe)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    nblk = int(16384 * target_s / dt)
+    nblk = max(16384, min(nblk, host.size // 8))
+    sample = np.ascontiguousarray(host[: 8 * nblk])
+    t0 = time.perf_counter()
+    oracle.tdes_ecb(key, sample)
+    dt = time.perf_counter() - t0
+    return {"value": sample.size / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d blocks (%.1f MiB) of the same input, 3DES-ECB encrypt, %.2f s"
+                      % (nblk, sample.size / 2**20, dt)}
+
+
+def traffic_from_profile(kernel, nbytes):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current kernel source and workload; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_1gib_pmc.md" % kernel)
+    if not os.path.exists(path) or nbytes != GIB:
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("bench-traffic:"):
+                for kv in line.split(":", 1)[1].split():
+                    k, v = kv.split("=")
+                    fields[k] = v
+    src = os.path.join(ROOT, "paper_2007_10752_amd", "csrc", "%s.hip" % kernel)
+    gen = os.path.join(ROOT, "paper_2007_10752_amd", "csrc", "generated", "%s_gen.h" % kernel)
+    h = hashlib.sha256()
+    for p in (src, gen):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    if fields.get("source_sha256") != h.hexdigest()[:16]:
+        return None
+    return float(fields["bytes_per_launch"])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: ECB needs no exchange between GPUs, and this "
+              "build runs on a single MI355X (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2007_10752_amd import costs
+    from paper_2007_10752_amd import tdes
+    from paper_2007_10752_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nbytes = args.nbytes
+    assert nbytes % 8 == 0
+    key = W.key_bundle(W.rng(W.SEED_BASE + 2 + W.KEY_SEED_OFFSET))
+    if args.input == "uniform":
+        host = W.uniform_bytes(W.rng(W.SEED_BASE + 2), nbytes)
+    elif args.input == "zero":
+        host = np.zeros(nbytes, np.uint8)
+    else:
+        host = W.pattern_bytes(nbytes)
+    x = torch.from_numpy(host).cuda()
+    out = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    kernel = tdes.KERNELS[args.kernel]
+
+    def step():
+        sched = tdes.key_schedule(key)
+        tdes.ecb_crypt_ptr(sched, tdes.ENCRYPT, kernel, x.data_ptr(), out.data_ptr(), nbytes, sh)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("warmup done", file=sys.stderr, flush=True)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    print("timed %d steps: %.3f ms/step" % (args.steps, wall / args.steps * 1e3),
+          file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del y
+
+    nblocks = nbytes // 8
+    value = nbytes * args.steps / wall / 1e9
+    ops = costs.ops_per_block(args.kernel) * nblocks
+    achieved = ops / avg_kernel_s
+    traffic = traffic_from_profile(args.kernel, nbytes)
+    line = {
+        "metric": "3DES-ECB GB/s at 1 GiB (bit-exact); batched/served GB/s + p50/p99 vs plain",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "3des-ede-ecb-encrypt", "bytes": nbytes, "blocks": nblocks,
+                   "input": args.input, "key": "3-key", "kernel": args.kernel,
+                   "seed": W.SEED_BASE + 2},
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved / 1e12, 3),
+            "peak": round(costs.VALU_PEAK_OPS / 1e12, 3),
+            "unit": "T lane-ops/s (32-bit VALU)",
+            "frac": round(achieved / costs.VALU_PEAK_OPS, 4),
+            "traffic": traffic,
+            "ops_per_block": round(costs.ops_per_block(args.kernel), 2),
+            "kernel_ms": round(avg_kernel_s * 1e3, 4),
+            "hbm_gbps": round(costs.HBM_BYTES_PER_BLOCK * nblocks / avg_kernel_s / 1e9, 2),
+            "hbm_frac": round(costs.HBM_BYTES_PER_BLOCK * nblocks / avg_kernel_s
+                              / costs.HBM_PEAK_BYTES, 4),
+        },
+    }
+    if args.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(key, host, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

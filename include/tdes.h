@@ -1,0 +1,102 @@
+/*
+ * tdes.h - Triple-DES (EDE) over independent 64-bit blocks on one AMD
+ * Instinct MI355X (gfx950), C ABI.
+ *
+ * Method: the DES key schedule (Sec. III-A of the paper: PC-1, cumulative
+ * left rotations by the shift table, PC-2, 16 round keys per base key),
+ * DES block encryption and decryption (Sec. III-B: IP, 16 Feistel rounds of
+ * expansion, key mixing, S-boxes and the straight permutation, R16 || L16,
+ * FP; decryption uses the round keys in reverse), composed as 3DES-EDE
+ *     C = E_K3(D_K2(E_K1(P))),   P = D_K1(E_K2(D_K3(C)))   (Sec. III-B)
+ * and applied to every 8-byte block independently (ECB, Sec. V).
+ *
+ * Conventions
+ *   - DES bit 1 is the most significant bit of byte 0 of a key or block.
+ *   - A key bundle is 24 bytes K1 || K2 || K3; 2-key 3DES is K1 || K2 || K1.
+ *     Parity bits (bit 8 of every key byte) are ignored, never checked.
+ *   - Lengths are in bytes and must be a multiple of 8; no padding is added.
+ *   - Device pointers are plain HIP device addresses (for example the
+ *     data_ptr() of a torch tensor); the caller owns every buffer.  The
+ *     library allocates nothing on the encryption path.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device calls
+ *     only enqueue work and return; results are valid once the stream has
+ *     completed the work.
+ *   - Argument errors are reported synchronously, before any device work is
+ *     enqueued; a failed launch returns TDES_ERR_DEVICE.  tdes_last_error()
+ *     gives a message for the last failure on the calling thread.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef TDES_H
+#define TDES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDES_ABI_VERSION 1
+
+typedef enum {
+    TDES_OK = 0,
+    TDES_ERR_ARG = -1,        /* NULL pointer or bad enum value            */
+    TDES_ERR_LENGTH = -2,     /* byte count not a multiple of 8            */
+    TDES_ERR_ALIGN = -3,      /* device pointer not 8-byte aligned         */
+    TDES_ERR_OVERLAP = -4,    /* input and output overlap but differ       */
+    TDES_ERR_NOMEM = -5,      /* reserved: the library does not allocate   */
+    TDES_ERR_DEVICE = -6      /* HIP reported an error; see last_error     */
+} tdes_status;
+
+typedef enum { TDES_ENCRYPT = 0, TDES_DECRYPT = 1 } tdes_dir;
+
+/* Kernel selection for tdes_ecb_crypt. */
+typedef enum {
+    TDES_KERNEL_AUTO = 0,     /* the library's choice (bitsliced)          */
+    TDES_KERNEL_BITSLICE = 1, /* 32 blocks per lane as bit planes; S-boxes
+                                 as gate networks, E/P/IP/FP as renaming   */
+    TDES_KERNEL_SPBOX = 2     /* one block per lane; S-box+P tables in LDS */
+} tdes_kernel;
+
+/* Round keys of a key bundle, Sec. III-A.  k[b][i] is round key i+1 (of 16)
+ * of base key K(b+1), 48 bits, with round-key bit 1 as bit 47 of the value.
+ * A plain value type: copy it, keep it on the host. */
+typedef struct {
+    uint64_t k[3][16];
+} tdes_schedule;
+
+/* Key generation (Sec. III-A) for the 24-byte bundle key24 (host memory).
+ * Synchronous, host only.  Errors: TDES_ERR_ARG on NULL. */
+tdes_status tdes_key_schedule(const uint8_t key24[24], tdes_schedule *out);
+
+/* 3DES-EDE ECB encryption of nbytes bytes at device address d_in into
+ * d_out (Sec. III-B; ECB, Sec. V).  d_in == d_out (in place) is allowed;
+ * any other overlap is TDES_ERR_OVERLAP.  nbytes == 0 is a no-op.
+ * Errors: TDES_ERR_ARG (NULL ks or buffers with nbytes > 0),
+ * TDES_ERR_LENGTH (nbytes % 8), TDES_ERR_ALIGN (pointer % 8),
+ * TDES_ERR_OVERLAP, TDES_ERR_DEVICE (launch failure). */
+tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
+                             size_t nbytes, void *stream);
+
+/* 3DES-EDE ECB decryption; same arguments and errors as tdes_ecb_encrypt. */
+tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
+                             size_t nbytes, void *stream);
+
+/* Encryption or decryption (dir) with an explicit kernel choice; same
+ * arguments and errors as tdes_ecb_encrypt, plus TDES_ERR_ARG for a bad
+ * dir or kernel value. */
+tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const void *d_in,
+                           void *d_out, size_t nbytes, void *stream);
+
+/* Message of the last failed call on this thread ("" if none).  The
+ * pointer stays valid until the next library call on this thread. */
+const char *tdes_last_error(void);
+
+/* TDES_ABI_VERSION of the built library. */
+int tdes_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDES_H */

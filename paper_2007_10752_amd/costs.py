@@ -1,0 +1,52 @@
+"""Algorithmic work per 64-bit block of each kernel, for roofline figures.
+
+Counted from the generated code, in 32-bit VALU lane operations (one
+v_bitop3_b32 / v_xor_b32 / v_perm_b32 ... on one lane):
+
+bitsliced (per 32 blocks = one lane):
+  48 rounds x (S-box gates + 48 key XORs + 32 XORs into the other half)
+  + 4 transposes of 32 words (2 in, 2 out), each 16 pairs x
+    (2 + 2 + 4 + 4 + 4) ops (byte stages by v_perm_b32, bit stages by
+    shift + bit-field insert)
+  IP, E, P and FP are register renaming: no operations.
+table (SP-box) kernel (per block):
+  48 rounds x (1 rotate + 4 key XORs + 8 index extracts + 8 XORs)
+  + IP and FP rotate-and-mask groups (2 ops each); plus 8 LDS reads a round.
+HBM traffic: every block is read once and written once: 16 bytes.
+"""
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GEN = os.path.join(HERE, "csrc", "generated")
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 32-bit VALU lane-ops/s
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_BYTES = 8.0e12
+HBM_BYTES_PER_BLOCK = 16
+TRANSPOSE_OPS = 16 * (2 + 2 + 4 + 4 + 4)
+
+
+def _read(name):
+    with open(os.path.join(GEN, name)) as f:
+        return f.read()
+
+
+def sbox_gates_per_round():
+    m = re.search(r"#define BS_SBOX_GATES_PER_ROUND (\d+)", _read("bitslice_gen.h"))
+    return int(m.group(1))
+
+
+def bitslice_ops_per_block():
+    per_lane = 48 * (sbox_gates_per_round() + 48 + 32) + 4 * TRANSPOSE_OPS
+    return per_lane / 32.0
+
+
+def spbox_ops_per_block():
+    text = _read("spbox_gen.h")
+    groups = sum(int(g) for g in re.findall(r"\((\d+) rotate-and-mask groups\)", text))
+    return 48 * (1 + 4 + 8 + 8) + 2 * groups
+
+
+def ops_per_block(kernel):
+    return spbox_ops_per_block() if kernel == "spbox" else bitslice_ops_per_block()

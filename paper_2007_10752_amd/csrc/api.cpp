@@ -1,0 +1,91 @@
+// C-ABI entry points of libtdes (declared in include/tdes.h): argument
+// checks, key formats, kernel dispatch, error reporting.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tdes_status fail(tdes_status st, const char *fmt, ...) {
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+// Checks shared by every call that takes a device in/out buffer pair.
+tdes_status check_buffers(const void *in, const void *out, size_t nbytes) {
+    if (nbytes % 8 != 0)
+        return fail(TDES_ERR_LENGTH, "length %zu is not a multiple of the 8-byte block", nbytes);
+    if (nbytes == 0) return TDES_OK;
+    if (in == nullptr || out == nullptr) return fail(TDES_ERR_ARG, "NULL data pointer");
+    const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+    if ((a | b) % 8 != 0) return fail(TDES_ERR_ALIGN, "data pointers must be 8-byte aligned");
+    if (a != b && a < b + nbytes && b < a + nbytes)
+        return fail(TDES_ERR_OVERLAP, "input and output overlap without being identical");
+    return TDES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdes_status tdes_key_schedule(const uint8_t key24[24], tdes_schedule *out) {
+    g_last_error.clear();
+    if (key24 == nullptr || out == nullptr) return fail(TDES_ERR_ARG, "NULL key or schedule");
+    for (int b = 0; b < 3; b++) tdes::des_round_keys(key24 + 8 * b, out->k[b]);
+    return TDES_OK;
+}
+
+tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const void *d_in,
+                           void *d_out, size_t nbytes, void *stream) {
+    g_last_error.clear();
+    if (ks == nullptr) return fail(TDES_ERR_ARG, "NULL schedule");
+    if (dir != TDES_ENCRYPT && dir != TDES_DECRYPT) return fail(TDES_ERR_ARG, "bad direction %d", dir);
+    if (kernel < TDES_KERNEL_AUTO || kernel > TDES_KERNEL_SPBOX)
+        return fail(TDES_ERR_ARG, "bad kernel %d", kernel);
+    tdes_status st = check_buffers(d_in, d_out, nbytes);
+    if (st != TDES_OK || nbytes == 0) return st;
+
+    tdes::RoundSequence seq;
+    tdes::round_sequence(*ks, dir, &seq);
+    const uint8_t *in = static_cast<const uint8_t *>(d_in);
+    uint8_t *out = static_cast<uint8_t *>(d_out);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (kernel == TDES_KERNEL_SPBOX) {
+        tdes::SpboxKeys k;
+        tdes::spbox_keys(seq, &k);
+        e = tdes::launch_spbox(k, in, out, nbytes, s);
+    } else {
+        tdes::BitsliceKeys k;
+        tdes::bitslice_keys(seq, &k);
+        e = tdes::launch_bitslice(k, in, out, nbytes, s);
+    }
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
+tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
+                             size_t nbytes, void *stream) {
+    return tdes_ecb_crypt(ks, TDES_ENCRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);
+}
+
+tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
+                             size_t nbytes, void *stream) {
+    return tdes_ecb_crypt(ks, TDES_DECRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);
+}
+
+const char *tdes_last_error(void) { return g_last_error.c_str(); }
+
+int tdes_abi_version(void) { return TDES_ABI_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side DES key schedule (Sec. III-A) and the per-kernel key formats.
+#include <string.h>
+
+#include "generated/des_tables_gen.h"
+#include "internal.h"
+
+namespace tdes {
+
+// Gather `nout` bits from the `nin`-bit value `in` (bit 1 = most
+// significant): output bit j is input bit table[j-1].
+static uint64_t gather(uint64_t in, int nin, const uint8_t *table, int nout) {
+    uint64_t out = 0;
+    for (int j = 0; j < nout; j++) out = (out << 1) | ((in >> (nin - table[j])) & 1u);
+    return out;
+}
+
+static uint32_t rotl28(uint32_t v, int s) {
+    return ((v << s) | (v >> (28 - s))) & 0x0FFFFFFFu;
+}
+
+void des_round_keys(const uint8_t key[8], uint64_t rk[16]) {
+    uint64_t k = 0;
+    for (int i = 0; i < 8; i++) k = (k << 8) | key[i];
+    const uint64_t cd = gather(k, 64, kPC1, 56);          // parity bits dropped
+    uint32_t c = (uint32_t)(cd >> 28), d = (uint32_t)(cd & 0x0FFFFFFFu);
+    for (int i = 0; i < 16; i++) {
+        c = rotl28(c, kShifts[i]);                         // cumulative
+        d = rotl28(d, kShifts[i]);
+        rk[i] = gather(((uint64_t)c << 28) | d, 56, kPC2, 48);
+    }
+}
+
+// Encryption: E_K1, D_K2, E_K3.  Decryption: D_K3, E_K2, D_K1.
+void round_sequence(const tdes_schedule &ks, int dir, RoundSequence *seq) {
+    static const int kKey[2][3] = {{0, 1, 2}, {2, 1, 0}};
+    static const int kRev[2][3] = {{0, 1, 0}, {1, 0, 1}};
+    for (int st = 0; st < 3; st++) {
+        const uint64_t *k = ks.k[kKey[dir][st]];
+        for (int r = 0; r < 16; r++) seq->rk[16 * st + r] = k[kRev[dir][st] ? 15 - r : r];
+    }
+}
+
+void bitslice_keys(const RoundSequence &seq, BitsliceKeys *out) {
+    for (int r = 0; r < 48; r++) {
+        uint64_t rev = 0;  // bit j = round-key bit j+1
+        for (int j = 0; j < 48; j++) rev |= ((seq.rk[r] >> (47 - j)) & 1u) << j;
+        out->lo[r] = (uint32_t)rev;
+        out->hi[r] = (uint32_t)(rev >> 32);
+    }
+}
+
+// Key chunk s (bits 6s+1..6s+6 of the round key) lines up with S-box window
+// s of the right half R (bit i of R at position 32 - i):
+//   windows 1..6 sit at positions 27-4s .. 32-4s of R; odd and even windows
+//   are disjoint, so one word carries the odd chunks and one the even ones;
+//   windows 0 and 7 wrap around, and are read from R rotated left by 7,
+//   at positions 2..7 and 6..11.
+void spbox_keys(const RoundSequence &seq, SpboxKeys *out) {
+    for (int r = 0; r < 48; r++) {
+        uint32_t ke = 0, ko = 0;
+        for (int s = 1; s <= 6; s++) {
+            const uint32_t ch = (uint32_t)((seq.rk[r] >> (42 - 6 * s)) & 0x3Fu);
+            if (s & 1) ko |= ch << (27 - 4 * s);
+            else ke |= ch << (27 - 4 * s);
+        }
+        out->ke[r] = ke;
+        out->ko[r] = ko;
+        out->k0[r] = (uint32_t)((seq.rk[r] >> 42) & 0x3Fu) << 2;
+        out->k7[r] = (uint32_t)(seq.rk[r] & 0x3Fu) << 6;
+    }
+}
+
+}  // namespace tdes

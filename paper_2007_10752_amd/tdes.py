@@ -1,0 +1,127 @@
+"""ctypes binding of libtdes.so (C ABI in include/tdes.h).
+
+Argument marshalling only: key bytes and schedules are passed through,
+tensors are turned into device pointers and streams into hipStream_t
+handles.  Every step of the cipher runs in the library's HIP kernels; there
+is no CPU fallback, and a missing library is an error.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtdes.so")
+
+ENCRYPT, DECRYPT = 0, 1
+KERNEL_AUTO, KERNEL_BITSLICE, KERNEL_SPBOX = 0, 1, 2
+KERNELS = {"auto": KERNEL_AUTO, "bitslice": KERNEL_BITSLICE, "spbox": KERNEL_SPBOX}
+
+STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR_ALIGN",
+          -4: "TDES_ERR_OVERLAP", -5: "TDES_ERR_NOMEM", -6: "TDES_ERR_DEVICE"}
+
+# Exported symbols, checked against include/tdes.h by the tests.
+SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
+           "tdes_last_error", "tdes_abi_version")
+
+
+class TdesError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, message))
+        self.status = status
+
+
+class Schedule(ctypes.Structure):
+    """tdes_schedule: k[b][i] = round key i+1 of base key b+1 (48 bits)."""
+    _fields_ = [("k", (ctypes.c_uint64 * 16) * 3)]
+
+    def round_keys(self):
+        return [[int(self.k[b][i]) for i in range(16)] for b in range(3)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("%s is missing: build it with `python -m paper_2007_10752_amd.build`"
+                               % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        sched_p = ctypes.POINTER(Schedule)
+        L.tdes_key_schedule.argtypes = [ctypes.POINTER(ctypes.c_uint8), sched_p]
+        L.tdes_key_schedule.restype = ctypes.c_int
+        for name in ("tdes_ecb_encrypt", "tdes_ecb_decrypt"):
+            fn = getattr(L, name)
+            fn.argtypes = [sched_p, vp, vp, sz, vp]
+            fn.restype = ctypes.c_int
+        L.tdes_ecb_crypt.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, vp, sz, vp]
+        L.tdes_ecb_crypt.restype = ctypes.c_int
+        L.tdes_last_error.argtypes = []
+        L.tdes_last_error.restype = ctypes.c_char_p
+        L.tdes_abi_version.argtypes = []
+        L.tdes_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise TdesError(status, lib().tdes_last_error().decode(errors="replace"))
+
+
+def key_schedule(key24):
+    """tdes_key_schedule on a 24-byte key bundle K1||K2||K3."""
+    kb = bytes(bytearray(key24))
+    if len(kb) != 24:
+        raise ValueError("key bundle must be 24 bytes")
+    buf = (ctypes.c_uint8 * 24).from_buffer_copy(kb)
+    s = Schedule()
+    _check(lib().tdes_key_schedule(buf, ctypes.byref(s)))
+    return s
+
+
+def ecb_crypt_ptr(schedule, direction, kernel, d_in, d_out, nbytes, stream=0):
+    """tdes_ecb_crypt on raw device addresses (ints) and a hipStream_t (int)."""
+    _check(lib().tdes_ecb_crypt(ctypes.byref(schedule), int(direction), int(kernel),
+                                ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                                ctypes.c_size_t(nbytes), ctypes.c_void_p(stream)))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _schedule(key):
+    return key if isinstance(key, Schedule) else key_schedule(key)
+
+
+def ecb(key, x, out=None, decrypt=False, kernel="auto", stream=None):
+    """3DES-EDE ECB over a contiguous uint8 CUDA tensor (length a multiple of
+    8).  ``key`` is a 24-byte bundle or a Schedule; ``out`` may be ``x``
+    (in place) or a new tensor is allocated.  Enqueued on ``stream`` (default:
+    torch's current stream)."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.uint8 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous uint8 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    if not (out.is_cuda and out.dtype == torch.uint8 and out.is_contiguous()
+            and out.numel() == x.numel()):
+        raise ValueError("out must be a contiguous uint8 CUDA tensor shaped like x")
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    ecb_crypt_ptr(_schedule(key), DECRYPT if decrypt else ENCRYPT, k,
+                  x.data_ptr(), out.data_ptr(), x.numel(), _stream_handle(stream))
+    return out
+
+
+def encrypt(key, x, out=None, kernel="auto", stream=None):
+    return ecb(key, x, out, False, kernel, stream)
+
+
+def decrypt(key, x, out=None, kernel="auto", stream=None):
+    return ecb(key, x, out, True, kernel, stream)

@@ -1,0 +1,185 @@
+"""CPU emulation of the two HIP kernels' arithmetic, built from the same
+generated headers the kernels compile (renaming maps, gate networks, SP
+tables, IP/FP code) and the same key formats.  Used by the host tests to
+check the generator and the key formats before anything runs on a GPU; the
+GPU parity tests then check the hardware path itself.
+"""
+import os
+import re
+
+import numpy as np
+
+from paper_2007_10752_amd.gen import emit
+from paper_2007_10752_amd.gen.networks import load_networks
+
+GEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_2007_10752_amd", "csrc", "generated")
+M32 = 0xFFFFFFFF
+
+
+def _header(name):
+    with open(os.path.join(GEN, name)) as f:
+        return f.read()
+
+
+def _int_array(text, name):
+    m = re.search(r"%s\[\d+\] = \{([^}]*)\}" % name, text)
+    return [int(v, 0) for v in m.group(1).replace("u", "").split(",") if v.strip()]
+
+
+# ---------------------------------------------------------------- keys ----
+
+def round_sequence(schedule, decrypt):
+    """48 round keys in application order (schedule: 3 x 16 ints)."""
+    keys = (2, 1, 0) if decrypt else (0, 1, 2)
+    rev = (1, 0, 1) if decrypt else (0, 1, 0)
+    seq = []
+    for st in range(3):
+        k = schedule[keys[st]]
+        seq += [k[15 - r] if rev[st] else k[r] for r in range(16)]
+    return seq
+
+
+# ------------------------------------------------------------ bitsliced ----
+
+def _lut3(imm, a, b, c):
+    r = 0
+    for idx in range(8):
+        if (imm >> idx) & 1:
+            r |= (a if idx & 4 else ~a) & (b if idx & 2 else ~b) & (c if idx & 1 else ~c)
+    return r & M32
+
+
+def _transpose32(x):
+    return [sum(((x[b] >> p) & 1) << b for b in range(32)) for p in range(32)]
+
+
+def bitslice_ecb(schedule, data, decrypt=False):
+    """Emulate tdes_bitslice_kernel on up to 32 blocks (one lane)."""
+    text = _header("bitslice_gen.h")
+    ip_l, ip_r = _int_array(text, "BS_IP_L"), _int_array(text, "BS_IP_R")
+    fp_src = _int_array(text, "BS_FP_SRC")
+    nets = load_networks()
+    import paper_2007_10752_amd.gen.des_tables as T
+    pinv = {T.P[j] - 1: j for j in range(32)}
+
+    d = np.asarray(data, dtype=np.uint8)
+    nblk = d.size // 8
+    assert nblk <= 32
+    words = np.zeros(64, dtype=np.uint32)
+    words[:2 * nblk] = d.view("<u4")
+    h0 = [int(words[2 * b]) for b in range(32)]
+    h1 = [int(words[2 * b + 1]) for b in range(32)]
+    h0, h1 = _transpose32(h0), _transpose32(h1)
+    plane = h0 + h1
+    X = [plane[i] for i in ip_l]
+    Y = [plane[i] for i in ip_r]
+
+    def rnd(dst, src, rk):
+        for box in range(8):
+            sig = []
+            for q in range(6):
+                e = 6 * box + q
+                kbit = (rk >> (47 - e)) & 1
+                sig.append(src[T.E[e] - 1] ^ (M32 if kbit else 0))
+            for a, b, c, imm in nets[box]["gates"]:
+                sig.append(_lut3(imm, sig[a], sig[b], sig[c]))
+            for q, (s, neg) in enumerate(nets[box]["outs"]):
+                dst[pinv[4 * box + q]] ^= (sig[s] ^ (M32 if neg else 0))
+
+    seq = round_sequence(schedule, decrypt)
+    for r in range(16):
+        rnd(X, Y, seq[r]) if r % 2 == 0 else rnd(Y, X, seq[r])
+    for r in range(16, 32):
+        rnd(Y, X, seq[r]) if r % 2 == 0 else rnd(X, Y, seq[r])
+    for r in range(32, 48):
+        rnd(X, Y, seq[r]) if r % 2 == 0 else rnd(Y, X, seq[r])
+    pre = Y + X
+    out_planes = [pre[fp_src[q]] for q in range(64)]
+    o0, o1 = _transpose32(out_planes[:32]), _transpose32(out_planes[32:])
+    ow = np.zeros(64, dtype=np.uint32)
+    for b in range(32):
+        ow[2 * b], ow[2 * b + 1] = o0[b], o1[b]
+    return ow.view(np.uint8)[:8 * nblk].copy()
+
+
+# ------------------------------------------------------------ table kernel --
+
+def spbox_keys(seq):
+    ke, ko, k0, k7 = [], [], [], []
+    for rk in seq:
+        e = o = 0
+        for s in range(1, 7):
+            ch = (rk >> (42 - 6 * s)) & 0x3F
+            if s & 1:
+                o |= ch << (27 - 4 * s)
+            else:
+                e |= ch << (27 - 4 * s)
+        ke.append(e)
+        ko.append(o)
+        k0.append(((rk >> 42) & 0x3F) << 2)
+        k7.append((rk & 0x3F) << 6)
+    return ke, ko, k0, k7
+
+
+def _rotl(x, s):
+    return ((x << s) | (x >> (32 - s))) & M32
+
+
+def _run_macro(text, name, env):
+    """Execute one of the generated IP/FP macros on Python ints."""
+    m = re.search(r"#define %s\([^)]*\) do \{ \\\n(.*?)\} while \(0\)" % name, text, re.S)
+    for line in m.group(1).split("\\\n"):
+        line = line.strip().rstrip(";")
+        if not line:
+            continue
+        line = re.sub(r"__builtin_amdgcn_alignbit\((\w+), \w+, (\d+)\)",
+                      lambda mm: "rotr(%s, %s)" % (mm.group(1), mm.group(2)), line)
+        line = line.replace("0u", "0").replace("u ", " ")
+        line = re.sub(r"(0x[0-9a-f]+)u", r"\1", line)
+        exec(line, {"rotr": lambda x, s: ((x >> s) | (x << (32 - s))) & M32}, env)
+    return env
+
+
+def spbox_ecb(schedule, data, decrypt=False):
+    """Emulate tdes_spbox_kernel block by block."""
+    text = _header("spbox_gen.h")
+    sp = _int_array(text, "SP_TABLE")
+    ke, ko, k0, k7 = spbox_keys(round_sequence(schedule, decrypt))
+
+    def f(R, r):
+        ro, re_, rr = R ^ ko[r], R ^ ke[r], _rotl(R, 7)
+        a0, a7 = rr ^ k0[r], rr ^ k7[r]
+        idx = [(a0 >> 2) & 63, (ro >> 23) & 63, (re_ >> 19) & 63, (ro >> 15) & 63,
+               (re_ >> 11) & 63, (ro >> 7) & 63, (re_ >> 3) & 63, (a7 >> 6) & 63]
+        v = 0
+        for s in range(8):
+            v ^= sp[64 * s + idx[s]]
+        return v
+
+    d = np.asarray(data, dtype=np.uint8)
+    w = d.view("<u4")
+    out = np.zeros_like(w)
+    for b in range(d.size // 8):
+        env = _run_macro(text, "SP_IP", {"w0": int(w[2 * b]), "w1": int(w[2 * b + 1])})
+        X, Y = env["L"], env["R"]
+        for r in range(0, 16, 2):
+            X ^= f(Y, r)
+            Y ^= f(X, r + 1)
+        for r in range(16, 32, 2):
+            Y ^= f(X, r)
+            X ^= f(Y, r + 1)
+        for r in range(32, 48, 2):
+            X ^= f(Y, r)
+            Y ^= f(X, r + 1)
+        env = _run_macro(text, "SP_FP", {"Lf": X, "Rf": Y})
+        out[2 * b], out[2 * b + 1] = env["o0"], env["o1"]
+    return out.view(np.uint8).copy()
+
+
+def generated_headers_match():
+    """True if the committed headers equal what the emitter writes now."""
+    nets = load_networks()
+    want = {"des_tables_gen.h": emit.emit_tables(), "bitslice_gen.h": emit.emit_bitslice(nets),
+            "spbox_gen.h": emit.emit_spbox()}
+    return {name: _header(name) == text for name, text in want.items()}

@@ -1,0 +1,119 @@
+"""Host-side checks of the library: no GPU work is done here.
+
+* libtdes.so loads and exports every function include/tdes.h declares;
+* the library's key schedule equals the oracle's;
+* argument errors are reported before any device call;
+* the library's transcription of the Appendix A tables equals the oracle's;
+* the S-box networks are exhaustively right (against the oracle's S-boxes);
+* the committed generated headers are what the generator writes;
+* a CPU emulation of both kernels' arithmetic (from those headers) matches
+  the oracle.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_10752_amd import tdes as T
+from paper_2007_10752_amd import workloads as W
+from paper_2007_10752_amd.gen import des_tables as DT
+from paper_2007_10752_amd.gen.networks import evaluate, load_networks
+
+import emulate_kernels as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "tdes.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdes_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = T.lib()
+    declared = _header_functions()
+    assert declared, "no functions found in tdes.h"
+    assert sorted(T.SYMBOLS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.tdes_abi_version() == 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_key_schedule_matches_oracle(seed):
+    key = W.key_bundle(W.rng(W.SEED_BASE + 0xB00 + seed))
+    got = T.key_schedule(key).round_keys()
+    for b in range(3):
+        assert got[b] == oracle.key_schedule(key[8 * b: 8 * b + 8])
+
+
+def _crypt(nbytes, d_in=0x1000, d_out=0x100000, dir=0, kernel=0, sched=True):
+    s = T.key_schedule(bytes(24))
+    lib = T.lib()
+    return lib.tdes_ecb_crypt(ctypes.byref(s) if sched else None, dir, kernel,
+                              ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                              ctypes.c_size_t(nbytes), ctypes.c_void_p(0))
+
+
+def test_argument_errors_before_device_work():
+    # None of these reaches a HIP call (the addresses are never touched).
+    assert _crypt(12) == -2                       # TDES_ERR_LENGTH
+    assert _crypt(8, d_in=0x1004) == -3           # TDES_ERR_ALIGN
+    assert _crypt(64, d_in=0x1000, d_out=0x1008) == -4  # TDES_ERR_OVERLAP
+    assert _crypt(8, d_in=0, d_out=0x1000) == -1  # NULL buffer
+    assert _crypt(8, dir=2) == -1
+    assert _crypt(8, kernel=7) == -1
+    assert _crypt(8, sched=False) == -1
+    assert b"overlap" in _crypt_msg(64, 0x1000, 0x1008)
+    assert _crypt(0, d_in=0, d_out=0) == 0        # empty: no-op
+    assert T.lib().tdes_key_schedule(None, None) == -1
+
+
+def _crypt_msg(n, a, b):
+    _crypt(n, a, b)
+    return T.lib().tdes_last_error()
+
+
+def test_tables_match_oracle_transcription():
+    pairs = {"pc_1": DT.PC1, "shift_keys": DT.SHIFTS, "pc_2": DT.PC2, "initial_perm": DT.IP,
+             "exp_d": DT.E, "per": DT.P, "final_perm": DT.FP}
+    for name, mine in pairs.items():
+        assert oracle.table(name) == list(mine), name
+    flat = [v for box in DT.SBOX for row in box for v in row]
+    assert oracle.table("s") == flat
+
+
+def test_sbox_networks_exhaustive():
+    nets = load_networks()
+    for box in range(8):
+        for v in range(64):
+            assert evaluate(nets[box], v) == oracle.sbox(box, v), (box, v)
+
+
+def test_generated_headers_are_current():
+    assert all(E.generated_headers_match().values()), E.generated_headers_match()
+
+
+@pytest.mark.parametrize("two_key", [False, True])
+def test_bitslice_emulation_matches_oracle(two_key):
+    g = W.rng(W.SEED_BASE + 0xC00 + two_key)
+    key = W.key_bundle(g, two_key=two_key)
+    data = W.uniform_bytes(g, 8 * 29)  # a partial lane
+    sched = T.key_schedule(key).round_keys()
+    ct = E.bitslice_ecb(sched, data)
+    assert np.array_equal(ct, oracle.tdes_ecb(key, data))
+    assert np.array_equal(E.bitslice_ecb(sched, ct, decrypt=True), data)
+
+
+def test_spbox_emulation_matches_oracle():
+    g = W.rng(W.SEED_BASE + 0xC10)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 8 * 6)
+    sched = T.key_schedule(key).round_keys()
+    ct = E.spbox_ecb(sched, data)
+    assert np.array_equal(ct, oracle.tdes_ecb(key, data))
+    assert np.array_equal(E.spbox_ecb(sched, ct, decrypt=True), data)

@@ -88,6 +88,14 @@ tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_
 tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const void *d_in,
                            void *d_out, size_t nbytes, void *stream);
 
+/* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
+ * TDES_KERNEL_SPBOX; AUTO means the kernel AUTO selects) would receive for
+ * schedule ks and direction dir, copied to host memory `out` (cap bytes).
+ * Returns the number of bytes written, or a negative tdes_status
+ * (TDES_ERR_ARG for NULL pointers, bad enums or cap too small).  For
+ * inspection and testing: the encryption calls build it themselves. */
+long tdes_kernel_key_bytes(const tdes_schedule *ks, int dir, int kernel, void *out, size_t cap);
+
 /* Message of the last failed call on this thread ("" if none).  The
  * pointer stays valid until the next library call on this thread. */
 const char *tdes_last_error(void);

@@ -1,0 +1,45 @@
+/*
+ * tdes_probe.h - microbenchmarks for the hardware ceilings the 3DES kernels
+ * are reported against (not part of the cipher).
+ *
+ * The bitsliced kernel is bound by the 32-bit vector ALU: its rounds are
+ * v_bitop3_b32 gates and v_xor_b32 with a scalar key mask.  These probes
+ * measure how many such lane operations per second MI355X sustains, and the
+ * HBM bandwidth of a plain copy (also the reference kernel whose memory
+ * counters calibrate the cipher's measured HBM traffic).
+ *
+ * Same conventions as tdes.h: device pointers owned by the caller, work
+ * enqueued on `stream` (a hipStream_t, NULL = default), return 0 on success,
+ * -1 on a bad argument (nothing enqueued), -6 if the launch failed.
+ */
+#ifndef TDES_PROBE_H
+#define TDES_PROBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TDES_PROBE_BITOP3 = 0,   /* v_bitop3_b32, three vector operands        */
+    TDES_PROBE_XOR = 1,      /* v_xor_b32, two vector operands             */
+    TDES_PROBE_XOR_SGPR = 2  /* v_xor_b32 with one scalar operand          */
+};
+
+/* Launch `blocks` workgroups of 256 threads; every thread issues
+ * 16 * iters instructions of kind `op`, then writes one word to
+ * d_sink[block * 256 + thread] (d_sink holds blocks * 256 uint32).
+ * Lane operations performed: blocks * 256 * 16 * iters. */
+int tdes_probe_valu(int op, uint32_t *d_sink, unsigned blocks, unsigned iters, void *stream);
+
+/* Copy nbytes (multiple of 16; both pointers 16-byte aligned; buffers
+ * must not overlap) from d_in to d_out with 16-byte vector loads/stores. */
+int tdes_probe_copy(const void *d_in, void *d_out, size_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDES_PROBE_H */

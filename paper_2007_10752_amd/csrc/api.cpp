@@ -2,6 +2,7 @@
 // checks, key formats, kernel dispatch, error reporting.
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <string>
 
@@ -82,6 +83,28 @@ tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_
 tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
                              size_t nbytes, void *stream) {
     return tdes_ecb_crypt(ks, TDES_DECRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);
+}
+
+long tdes_kernel_key_bytes(const tdes_schedule *ks, int dir, int kernel, void *out, size_t cap) {
+    g_last_error.clear();
+    if (ks == nullptr || out == nullptr) return fail(TDES_ERR_ARG, "NULL schedule or buffer");
+    if (dir != TDES_ENCRYPT && dir != TDES_DECRYPT) return fail(TDES_ERR_ARG, "bad direction %d", dir);
+    if (kernel < TDES_KERNEL_AUTO || kernel > TDES_KERNEL_SPBOX)
+        return fail(TDES_ERR_ARG, "bad kernel %d", kernel);
+    tdes::RoundSequence seq;
+    tdes::round_sequence(*ks, dir, &seq);
+    if (kernel == TDES_KERNEL_SPBOX) {
+        tdes::SpboxKeys k;
+        if (cap < sizeof k) return fail(TDES_ERR_ARG, "buffer too small (%zu < %zu)", cap, sizeof k);
+        tdes::spbox_keys(seq, &k);
+        memcpy(out, &k, sizeof k);
+        return (long)sizeof k;
+    }
+    tdes::BitsliceKeys k;
+    if (cap < sizeof k) return fail(TDES_ERR_ARG, "buffer too small (%zu < %zu)", cap, sizeof k);
+    tdes::bitslice_keys(seq, &k);
+    memcpy(out, &k, sizeof k);
+    return (long)sizeof k;
 }
 
 const char *tdes_last_error(void) { return g_last_error.c_str(); }

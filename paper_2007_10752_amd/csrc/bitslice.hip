@@ -14,8 +14,10 @@
 // which word goes to which output plane.  The S-boxes (Sec. III-B) are
 // gate networks of v_bitop3_b32 (any boolean function of three inputs),
 // found by search and verified exhaustively at build time.  Key mixing is an
-// XOR with an all-zeros / all-ones mask made on the scalar unit from the
-// round key (uniform over the launch).  The three DES passes of EDE run back
+// XOR with all-zeros / all-ones masks (the key is uniform over the launch),
+// mostly folded into the XOR that adds an S-box output into the other half:
+// each half is kept XORed with the key bits its next round needs (the mask
+// bookkeeping is done on the host, see keysched.cpp).  The three DES passes of EDE run back
 // to back in registers: FP followed by IP is the identity, so the inner
 // permutations vanish and the R16 || L16 swap between passes is a change of
 // roles between the two halves.
@@ -23,6 +25,7 @@
 #include <stdint.h>
 
 #include "generated/bitslice_gen.h"
+#include "generated/bitslice_keys_gen.h"
 #include "internal.h"
 
 namespace tdes {
@@ -65,8 +68,16 @@ __device__ __forceinline__ void transpose32(uint32_t (&x)[32]) {
 }
 
 template <bool VEC16>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void tdes_bitslice_kernel(
-    const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
+__global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
+    // Expand the launch's key masks (bits) into 0 / ~0 words in LDS.  Read
+    // back with a uniform address they are broadcast to every lane and enter
+    // the VALU as vector operands (full issue rate; a scalar operand halves it).
+    __shared__ __align__(16) uint32_t km[kBsNumMasks];
+    for (int i = threadIdx.x; i < kBsNumMasks; i += kWave * kWavesPerBlock)
+        km[i] = 0u - ((keys.bits[i / 32] >> (i % 32)) & 1u);
+    __syncthreads();
+
     const size_t chunk = (size_t)blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
     const size_t base = chunk * kChunk;
     if (base >= nbytes) return;  // wave-uniform
@@ -101,27 +112,33 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_
 #pragma unroll
     for (int i = 0; i < 32; i++) {
         X[i] = BS_IP_L[i] < 32 ? h0[BS_IP_L[i]] : h1[BS_IP_L[i] - 32];
-        Y[i] = BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32];
+        Y[i] = (BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32]) ^ km[kBsInitY + i];
     }
 
     // Pass 1 (L = X, R = Y); ends with X = L16, Y = R16.
 #pragma unroll 1
     for (int r = 0; r < 16; r += 2) {
-        bs_round(X, Y, keys.lo[r], keys.hi[r]);
-        bs_round(Y, X, keys.lo[r + 1], keys.hi[r + 1]);
+        bs_round(X, Y, km + kBsRoundMasks * r);
+        bs_round(Y, X, km + kBsRoundMasks * (r + 1));
     }
     // Pass 2 starts from R16 || L16 of pass 1: L = Y, R = X.
+#pragma unroll
+    for (int i = 0; i < 32; i++) X[i] ^= km[kBsRemask16 + i];
 #pragma unroll 1
     for (int r = 16; r < 32; r += 2) {
-        bs_round(Y, X, keys.lo[r], keys.hi[r]);
-        bs_round(X, Y, keys.lo[r + 1], keys.hi[r + 1]);
+        bs_round(Y, X, km + kBsRoundMasks * r);
+        bs_round(X, Y, km + kBsRoundMasks * (r + 1));
     }
     // Pass 3: L = X, R = Y again; ends with X = L16, Y = R16.
+#pragma unroll
+    for (int i = 0; i < 32; i++) Y[i] ^= km[kBsRemask32 + i];
 #pragma unroll 1
     for (int r = 32; r < 48; r += 2) {
-        bs_round(X, Y, keys.lo[r], keys.hi[r]);
-        bs_round(Y, X, keys.lo[r + 1], keys.hi[r + 1]);
+        bs_round(X, Y, km + kBsRoundMasks * r);
+        bs_round(Y, X, km + kBsRoundMasks * (r + 1));
     }
+#pragma unroll
+    for (int i = 0; i < 32; i++) X[i] ^= km[kBsFinalX + i];
 
 #pragma unroll
     for (int q = 0; q < 32; q++) {

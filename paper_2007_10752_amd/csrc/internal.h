@@ -15,11 +15,12 @@ struct RoundSequence {
     uint64_t rk[48];  // 48-bit round keys, bit 1 = bit 47
 };
 
-// Kernel argument for the bitsliced kernel: round r's key bits 1..32 in
-// lo[r] bits 0..31 and bits 33..48 in hi[r] bits 0..15.
+// Kernel argument for the bitsliced kernel: the key masks of one launch
+// as bits (mask i is bit i % 32 of bits[i / 32]; layout in
+// generated/bitslice_keys_gen.h); the kernel expands them to 0 / ~0 words.
+constexpr int kBitsliceMaskWords = 76;
 struct BitsliceKeys {
-    uint32_t lo[48];
-    uint32_t hi[48];
+    uint32_t bits[kBitsliceMaskWords];
 };
 
 // Kernel argument for the table kernel: per round, the key chunks XORed into

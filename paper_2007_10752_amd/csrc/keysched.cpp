@@ -1,6 +1,7 @@
 // Host-side DES key schedule (Sec. III-A) and the per-kernel key formats.
 #include <string.h>
 
+#include "generated/bitslice_keys_gen.h"
 #include "generated/des_tables_gen.h"
 #include "internal.h"
 
@@ -40,13 +41,59 @@ void round_sequence(const tdes_schedule &ks, int dir, RoundSequence *seq) {
     }
 }
 
+// The bitsliced kernel keeps each half XORed with a key mask so that key
+// mixing costs no separate operation for most S-box inputs:
+//   - a word of the source half carries the round-key bit of its primary
+//     expansion position (the first of the one or two positions that read
+//     it); its second position, if any, XORs the difference of the two bits;
+//   - when a word of the destination half is updated, the XOR that adds the
+//     S-box output also swaps its old mask for the one its next use as a
+//     source needs (0 after its last use);
+//   - the three fixed extra steps: mask R after IP, re-mask the source half
+//     where a DES pass starts with a source already used by the previous
+//     round (rounds 16 and 32), and unmask X at the end.
+// Round t updates D from S: rounds of passes 1 and 3 alternate X^=f(Y),
+// Y^=f(X); pass 2 starts from the swapped halves, Y^=f(X), X^=f(Y), ...
+static bool dest_is_x(int t) { return ((t / 16) % 2 == 0) == (t % 2 == 0); }
+
 void bitslice_keys(const RoundSequence &seq, BitsliceKeys *out) {
-    for (int r = 0; r < 48; r++) {
-        uint64_t rev = 0;  // bit j = round-key bit j+1
-        for (int j = 0; j < 48; j++) rev |= ((seq.rk[r] >> (47 - j)) & 1u) << j;
-        out->lo[r] = (uint32_t)rev;
-        out->hi[r] = (uint32_t)(rev >> 32);
+    memset(out, 0, sizeof *out);
+    auto kbit = [&](int t, int e) { return (uint32_t)((seq.rk[t] >> (47 - e)) & 1u); };
+    auto put = [&](int idx, uint32_t v) {
+        if (v) out->bits[idx / 32] |= 1u << (idx % 32);
+    };
+    uint32_t mx[32], my[32];
+    for (int i = 0; i < 32; i++) {
+        mx[i] = 0;
+        my[i] = kbit(0, kBsPrimaryE[i]);
+        put(kBsInitY + i, my[i]);
     }
+    for (int t = 0; t < 48; t++) {
+        const bool dx = dest_is_x(t);
+        uint32_t *ms = dx ? my : mx, *md = dx ? mx : my;
+        if (t == 16 || t == 32) {
+            const int base = t == 16 ? kBsRemask16 : kBsRemask32;
+            for (int i = 0; i < 32; i++) {
+                const uint32_t m = kbit(t, kBsPrimaryE[i]);
+                put(base + i, ms[i] ^ m);
+                ms[i] = m;
+            }
+        }
+        for (int k = 0; k < 16; k++) {
+            const int e = kBsDupE[k], j = kBsESrc[e];
+            put(kBsRoundMasks * t + 32 + k, ms[j] ^ kbit(t, e));
+        }
+        int next = -1;  // next round reading the half updated now
+        for (int u = t + 1; u < 48 && next < 0; u++)
+            if (dest_is_x(u) != dx) next = u;
+        for (int o = 0; o < 32; o++) {
+            const int i = kBsOutWord[o];
+            const uint32_t m = next < 0 ? 0u : kbit(next, kBsPrimaryE[i]);
+            put(kBsRoundMasks * t + o, md[i] ^ m);
+            md[i] = m;
+        }
+    }
+    for (int i = 0; i < 32; i++) put(kBsFinalX + i, mx[i]);
 }
 
 // Key chunk s (bits 6s+1..6s+6 of the round key) lines up with S-box window

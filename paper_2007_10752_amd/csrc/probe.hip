@@ -1,0 +1,82 @@
+// Microbenchmarks for the MI355X ceilings the cipher kernels are compared
+// against: the issue rate of the 32-bit VALU instructions the bitsliced
+// kernel is made of, and the HBM bandwidth of a plain copy.  Exported
+// through include/tdes_probe.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdes_probe.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kAcc = 16;  // independent accumulators per lane
+
+// Each iteration issues kAcc instructions of one kind; accumulator j reads
+// two others, so a sweep has kAcc-way instruction-level parallelism.
+template <int OP>
+__global__ __launch_bounds__(kThreads) void valu_probe_kernel(uint32_t *sink, uint32_t iters,
+                                                              uint32_t smask) {
+    uint32_t a[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; j++) a[j] = threadIdx.x * 0x9E3779B9u + j * 0x7F4A7C15u + blockIdx.x;
+    for (uint32_t i = 0; i < iters; i++) {
+#pragma unroll
+        for (int j = 0; j < kAcc; j++) {
+            if (OP == TDES_PROBE_BITOP3)
+                asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xe8"
+                             : "=v"(a[j]) : "v"(a[j]), "v"(a[(j + 1) % kAcc]), "v"(a[(j + 2) % kAcc]));
+            else if (OP == TDES_PROBE_XOR)
+                asm volatile("v_xor_b32 %0, %1, %2" : "=v"(a[j]) : "v"(a[j]), "v"(a[(j + 3) % kAcc]));
+            else
+                asm volatile("v_xor_b32 %0, %1, %2" : "=v"(a[j]) : "s"(smask), "v"(a[j]));
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < kAcc; j++) r ^= a[j];
+    sink[(size_t)blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void copy_probe_kernel(const uint4 *in, uint4 *out,
+                                                              size_t n16) {
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n16; i += stride)
+        out[i] = in[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+int tdes_probe_valu(int op, uint32_t *d_sink, unsigned blocks, unsigned iters, void *stream) {
+    if (d_sink == nullptr || blocks == 0 || iters == 0 || op < 0 || op > TDES_PROBE_XOR_SGPR)
+        return -1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (op == TDES_PROBE_BITOP3)
+        hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_BITOP3>, dim3(blocks), dim3(kThreads), 0,
+                           s, d_sink, iters, 0x5A5A5A5Au);
+    else if (op == TDES_PROBE_XOR)
+        hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_XOR>, dim3(blocks), dim3(kThreads), 0, s,
+                           d_sink, iters, 0x5A5A5A5Au);
+    else
+        hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_XOR_SGPR>, dim3(blocks), dim3(kThreads),
+                           0, s, d_sink, iters, 0x5A5A5A5Au);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+int tdes_probe_copy(const void *d_in, void *d_out, size_t nbytes, void *stream) {
+    if (d_in == nullptr || d_out == nullptr || nbytes % 16 != 0 ||
+        (((uintptr_t)d_in | (uintptr_t)d_out) & 15u) != 0)
+        return -1;
+    if (nbytes == 0) return 0;
+    const size_t n16 = nbytes / 16;
+    size_t grid = (n16 + kThreads * 4 - 1) / (kThreads * 4);
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)grid), dim3(kThreads), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const uint4 *>(d_in),
+                       static_cast<uint4 *>(d_out), n16);
+    return hipGetLastError() == hipSuccess ? 0 : -6;
+}
+
+}  // extern "C"

@@ -18,9 +18,10 @@ KERNELS = {"auto": KERNEL_AUTO, "bitslice": KERNEL_BITSLICE, "spbox": KERNEL_SPB
 STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR_ALIGN",
           -4: "TDES_ERR_OVERLAP", -5: "TDES_ERR_NOMEM", -6: "TDES_ERR_DEVICE"}
 
-# Exported symbols, checked against include/tdes.h by the tests.
+# Exported symbols, checked against include/*.h by the tests.
 SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
-           "tdes_last_error", "tdes_abi_version")
+           "tdes_last_error", "tdes_abi_version", "tdes_kernel_key_bytes", "tdes_probe_valu",
+           "tdes_probe_copy")
 
 
 class TdesError(RuntimeError):
@@ -62,6 +63,12 @@ def lib():
         L.tdes_last_error.restype = ctypes.c_char_p
         L.tdes_abi_version.argtypes = []
         L.tdes_abi_version.restype = ctypes.c_int
+        L.tdes_kernel_key_bytes.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, sz]
+        L.tdes_kernel_key_bytes.restype = ctypes.c_long
+        L.tdes_probe_valu.argtypes = [ctypes.c_int, vp, ctypes.c_uint, ctypes.c_uint, vp]
+        L.tdes_probe_valu.restype = ctypes.c_int
+        L.tdes_probe_copy.argtypes = [vp, vp, sz, vp]
+        L.tdes_probe_copy.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -87,6 +94,15 @@ def ecb_crypt_ptr(schedule, direction, kernel, d_in, d_out, nbytes, stream=0):
     _check(lib().tdes_ecb_crypt(ctypes.byref(schedule), int(direction), int(kernel),
                                 ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
                                 ctypes.c_size_t(nbytes), ctypes.c_void_p(stream)))
+
+
+def kernel_key_bytes(schedule, direction, kernel):
+    """The kernel argument a launch would receive (tdes_kernel_key_bytes)."""
+    buf = ctypes.create_string_buffer(4096)
+    n = lib().tdes_kernel_key_bytes(ctypes.byref(schedule), int(direction), int(kernel), buf, 4096)
+    if n < 0:
+        _check(int(n))
+    return buf.raw[:n]
 
 
 def _stream_handle(stream):

@@ -27,19 +27,6 @@ def _int_array(text, name):
     return [int(v, 0) for v in m.group(1).replace("u", "").split(",") if v.strip()]
 
 
-# ---------------------------------------------------------------- keys ----
-
-def round_sequence(schedule, decrypt):
-    """48 round keys in application order (schedule: 3 x 16 ints)."""
-    keys = (2, 1, 0) if decrypt else (0, 1, 2)
-    rev = (1, 0, 1) if decrypt else (0, 1, 0)
-    seq = []
-    for st in range(3):
-        k = schedule[keys[st]]
-        seq += [k[15 - r] if rev[st] else k[r] for r in range(16)]
-    return seq
-
-
 # ------------------------------------------------------------ bitsliced ----
 
 def _lut3(imm, a, b, c):
@@ -54,46 +41,69 @@ def _transpose32(x):
     return [sum(((x[b] >> p) & 1) << b for b in range(32)) for p in range(32)]
 
 
-def bitslice_ecb(schedule, data, decrypt=False):
-    """Emulate tdes_bitslice_kernel on up to 32 blocks (one lane)."""
+def _bs_masks(key_bytes):
+    bits = np.frombuffer(key_bytes, dtype="<u4")
+    n = _int_const(_header("bitslice_keys_gen.h"), "kBsNumMasks")
+    return [M32 if (int(bits[i // 32]) >> (i % 32)) & 1 else 0 for i in range(n)]
+
+
+def _int_const(text, name):
+    return int(re.search(r"%s = (\d+)" % name, text).group(1))
+
+
+def bitslice_ecb(key_bytes, data):
+    """Emulate tdes_bitslice_kernel on up to 32 blocks (one lane), given the
+    kernel's key argument (tdes_kernel_key_bytes)."""
     text = _header("bitslice_gen.h")
+    ktext = _header("bitslice_keys_gen.h")
     ip_l, ip_r = _int_array(text, "BS_IP_L"), _int_array(text, "BS_IP_R")
     fp_src = _int_array(text, "BS_FP_SRC")
+    e_src = _int_array(ktext, "kBsESrc")
+    dup_e = _int_array(ktext, "kBsDupE")
+    out_word = _int_array(ktext, "kBsOutWord")
+    c = {k: _int_const(ktext, k) for k in ("kBsRoundMasks", "kBsInitY", "kBsRemask16",
+                                           "kBsRemask32", "kBsFinalX")}
+    km = _bs_masks(key_bytes)
     nets = load_networks()
-    import paper_2007_10752_amd.gen.des_tables as T
-    pinv = {T.P[j] - 1: j for j in range(32)}
+    dup_of = {e: k for k, e in enumerate(dup_e)}
 
     d = np.asarray(data, dtype=np.uint8)
     nblk = d.size // 8
     assert nblk <= 32
     words = np.zeros(64, dtype=np.uint32)
     words[:2 * nblk] = d.view("<u4")
-    h0 = [int(words[2 * b]) for b in range(32)]
-    h1 = [int(words[2 * b + 1]) for b in range(32)]
-    h0, h1 = _transpose32(h0), _transpose32(h1)
+    h0 = _transpose32([int(words[2 * b]) for b in range(32)])
+    h1 = _transpose32([int(words[2 * b + 1]) for b in range(32)])
     plane = h0 + h1
     X = [plane[i] for i in ip_l]
-    Y = [plane[i] for i in ip_r]
+    Y = [plane[i] ^ km[c["kBsInitY"] + n] for n, i in enumerate(ip_r)]
 
-    def rnd(dst, src, rk):
+    def rnd(dst, src, t):
+        m = km[c["kBsRoundMasks"] * t:]
         for box in range(8):
             sig = []
             for q in range(6):
                 e = 6 * box + q
-                kbit = (rk >> (47 - e)) & 1
-                sig.append(src[T.E[e] - 1] ^ (M32 if kbit else 0))
-            for a, b, c, imm in nets[box]["gates"]:
-                sig.append(_lut3(imm, sig[a], sig[b], sig[c]))
-            for q, (s, neg) in enumerate(nets[box]["outs"]):
-                dst[pinv[4 * box + q]] ^= (sig[s] ^ (M32 if neg else 0))
+                v = src[e_src[e]]
+                sig.append(v ^ m[32 + dup_of[e]] if e in dup_of else v)
+            for a, b, cc, imm in nets[box]["gates"]:
+                sig.append(_lut3(imm, sig[a], sig[b], sig[cc]))
+            for q, (sg, neg) in enumerate(nets[box]["outs"]):
+                j = out_word[4 * box + q]
+                dst[j] ^= sig[sg] ^ (M32 if neg else 0) ^ m[4 * box + q]
 
-    seq = round_sequence(schedule, decrypt)
-    for r in range(16):
-        rnd(X, Y, seq[r]) if r % 2 == 0 else rnd(Y, X, seq[r])
-    for r in range(16, 32):
-        rnd(Y, X, seq[r]) if r % 2 == 0 else rnd(X, Y, seq[r])
-    for r in range(32, 48):
-        rnd(X, Y, seq[r]) if r % 2 == 0 else rnd(Y, X, seq[r])
+    for t in range(0, 16, 2):
+        rnd(X, Y, t)
+        rnd(Y, X, t + 1)
+    X = [v ^ km[c["kBsRemask16"] + i] for i, v in enumerate(X)]
+    for t in range(16, 32, 2):
+        rnd(Y, X, t)
+        rnd(X, Y, t + 1)
+    Y = [v ^ km[c["kBsRemask32"] + i] for i, v in enumerate(Y)]
+    for t in range(32, 48, 2):
+        rnd(X, Y, t)
+        rnd(Y, X, t + 1)
+    X = [v ^ km[c["kBsFinalX"] + i] for i, v in enumerate(X)]
     pre = Y + X
     out_planes = [pre[fp_src[q]] for q in range(64)]
     o0, o1 = _transpose32(out_planes[:32]), _transpose32(out_planes[32:])
@@ -105,21 +115,9 @@ def bitslice_ecb(schedule, data, decrypt=False):
 
 # ------------------------------------------------------------ table kernel --
 
-def spbox_keys(seq):
-    ke, ko, k0, k7 = [], [], [], []
-    for rk in seq:
-        e = o = 0
-        for s in range(1, 7):
-            ch = (rk >> (42 - 6 * s)) & 0x3F
-            if s & 1:
-                o |= ch << (27 - 4 * s)
-            else:
-                e |= ch << (27 - 4 * s)
-        ke.append(e)
-        ko.append(o)
-        k0.append(((rk >> 42) & 0x3F) << 2)
-        k7.append((rk & 0x3F) << 6)
-    return ke, ko, k0, k7
+def spbox_keys_from_bytes(key_bytes):
+    w = np.frombuffer(key_bytes, dtype="<u4").reshape(4, 48)
+    return [list(map(int, w[i])) for i in range(4)]
 
 
 def _rotl(x, s):
@@ -141,11 +139,11 @@ def _run_macro(text, name, env):
     return env
 
 
-def spbox_ecb(schedule, data, decrypt=False):
-    """Emulate tdes_spbox_kernel block by block."""
+def spbox_ecb(key_bytes, data):
+    """Emulate tdes_spbox_kernel block by block, given its key argument."""
     text = _header("spbox_gen.h")
     sp = _int_array(text, "SP_TABLE")
-    ke, ko, k0, k7 = spbox_keys(round_sequence(schedule, decrypt))
+    ke, ko, k0, k7 = spbox_keys_from_bytes(key_bytes)
 
     def f(R, r):
         ro, re_, rr = R ^ ko[r], R ^ ke[r], _rotl(R, 7)
@@ -181,5 +179,5 @@ def generated_headers_match():
     """True if the committed headers equal what the emitter writes now."""
     nets = load_networks()
     want = {"des_tables_gen.h": emit.emit_tables(), "bitslice_gen.h": emit.emit_bitslice(nets),
-            "spbox_gen.h": emit.emit_spbox()}
+            "bitslice_keys_gen.h": emit.emit_bitslice_keys(), "spbox_gen.h": emit.emit_spbox()}
     return {name: _header(name) == text for name, text in want.items()}

@@ -28,9 +28,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _header_functions():
-    text = open(os.path.join(ROOT, "include", "tdes.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tdes_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(tdes_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -71,6 +75,11 @@ def test_argument_errors_before_device_work():
     assert b"overlap" in _crypt_msg(64, 0x1000, 0x1008)
     assert _crypt(0, d_in=0, d_out=0) == 0        # empty: no-op
     assert T.lib().tdes_key_schedule(None, None) == -1
+    lib = T.lib()
+    assert lib.tdes_probe_valu(9, ctypes.c_void_p(0x1000), 1, 1, None) == -1
+    assert lib.tdes_probe_valu(0, None, 1, 1, None) == -1
+    assert lib.tdes_probe_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 24, None) == -1
+    assert lib.tdes_probe_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 32, None) == -1
 
 
 def _crypt_msg(n, a, b):
@@ -98,22 +107,33 @@ def test_generated_headers_are_current():
     assert all(E.generated_headers_match().values()), E.generated_headers_match()
 
 
+def _kk(key, dec, kernel):
+    return T.kernel_key_bytes(T.key_schedule(key), T.DECRYPT if dec else T.ENCRYPT, kernel)
+
+
 @pytest.mark.parametrize("two_key", [False, True])
 def test_bitslice_emulation_matches_oracle(two_key):
     g = W.rng(W.SEED_BASE + 0xC00 + two_key)
     key = W.key_bundle(g, two_key=two_key)
     data = W.uniform_bytes(g, 8 * 29)  # a partial lane
-    sched = T.key_schedule(key).round_keys()
-    ct = E.bitslice_ecb(sched, data)
+    ct = E.bitslice_ecb(_kk(key, False, T.KERNEL_BITSLICE), data)
     assert np.array_equal(ct, oracle.tdes_ecb(key, data))
-    assert np.array_equal(E.bitslice_ecb(sched, ct, decrypt=True), data)
+    pt = E.bitslice_ecb(_kk(key, True, T.KERNEL_BITSLICE), ct)
+    assert np.array_equal(pt, data)
 
 
 def test_spbox_emulation_matches_oracle():
     g = W.rng(W.SEED_BASE + 0xC10)
     key = W.key_bundle(g)
     data = W.uniform_bytes(g, 8 * 6)
-    sched = T.key_schedule(key).round_keys()
-    ct = E.spbox_ecb(sched, data)
+    ct = E.spbox_ecb(_kk(key, False, T.KERNEL_SPBOX), data)
     assert np.array_equal(ct, oracle.tdes_ecb(key, data))
-    assert np.array_equal(E.spbox_ecb(sched, ct, decrypt=True), data)
+    pt = E.spbox_ecb(_kk(key, True, T.KERNEL_SPBOX), ct)
+    assert np.array_equal(pt, data)
+
+
+def test_kernel_key_bytes_errors():
+    s = T.key_schedule(bytes(24))
+    buf = ctypes.create_string_buffer(16)
+    assert T.lib().tdes_kernel_key_bytes(ctypes.byref(s), 0, 1, buf, 16) == -1
+    assert T.lib().tdes_kernel_key_bytes(ctypes.byref(s), 3, 1, buf, 16) == -1

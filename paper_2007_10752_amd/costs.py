@@ -4,7 +4,8 @@ Counted from the generated code, in 32-bit VALU lane operations (one
 v_bitop3_b32 / v_xor_b32 / v_perm_b32 ... on one lane):
 
 bitsliced (per 32 blocks = one lane):
-  48 rounds x (S-box gates + 48 key XORs + 32 XORs into the other half)
+  48 rounds x (S-box gates + 32 three-input XORs of the outputs into the other
+  half, which also carry the key masks, + 16 key XORs of second-use inputs)
   + 4 transposes of 32 words (2 in, 2 out), each 16 pairs x
     (2 + 2 + 4 + 4 + 4) ops (byte stages by v_perm_b32, bit stages by
     shift + bit-field insert)
@@ -20,8 +21,12 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 GEN = os.path.join(HERE, "csrc", "generated")
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 32-bit VALU lane-ops/s
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X: 256 CUs x 4 SIMDs x 32 lanes/clock x 2.4 GHz, 32-bit VALU lane-ops/s.
+# Wave64 bitwise VALU instructions issue at 32 lanes per clock per SIMD (two
+# waves' instructions per 4-clock window); the probe kernels in
+# include/tdes_probe.h sustain ~77 T (v_xor_b32), above the 39.3 T that 16
+# lanes per clock would allow.
+VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
 HBM_BYTES_PER_BLOCK = 16
 TRANSPOSE_OPS = 16 * (2 + 2 + 4 + 4 + 4)
@@ -37,8 +42,13 @@ def sbox_gates_per_round():
     return int(m.group(1))
 
 
+def xors_per_round():
+    m = re.search(r"#define BS_XORS_PER_ROUND (\d+)", _read("bitslice_gen.h"))
+    return int(m.group(1))
+
+
 def bitslice_ops_per_block():
-    per_lane = 48 * (sbox_gates_per_round() + 48 + 32) + 4 * TRANSPOSE_OPS
+    per_lane = 48 * (sbox_gates_per_round() + xors_per_round()) + 4 * TRANSPOSE_OPS
     return per_lane / 32.0
 
 

@@ -28,6 +28,10 @@
 #include "generated/bitslice_keys_gen.h"
 #include "internal.h"
 
+#ifndef TDES_BS_MIN_WAVES
+#define TDES_BS_MIN_WAVES 3  // waves per SIMD the register budget must allow
+#endif
+
 namespace tdes {
 
 namespace {
@@ -35,6 +39,10 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr size_t kChunk = 16384;  // bytes per wave
+// Buffer-resource word 3 for gfx9-family raw (unstructured) buffers.
+constexpr int kBufferFlags = 0x00020000;
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
 // One swap-move stage of the 32x32 transpose: rows i and i+J (i & J == 0)
 // exchange the J-bit groups where row bit J differs from column bit J.
@@ -68,7 +76,7 @@ __device__ __forceinline__ void transpose32(uint32_t (&x)[32]) {
 }
 
 template <bool VEC16>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
 void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
     // Expand the launch's key masks (bits) into 0 / ~0 words in LDS.  Read
     // back with a uniform address they are broadcast to every lane and enter
@@ -78,32 +86,44 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
         km[i] = 0u - ((keys.bits[i / 32] >> (i % 32)) & 1u);
     __syncthreads();
 
-    const size_t chunk = (size_t)blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
+    // the wave index is uniform within the wave; say so, so the chunk base
+    // and the buffer resources below live in scalar registers
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const size_t chunk = (size_t)blockIdx.x * kWavesPerBlock + wave;
     const size_t base = chunk * kChunk;
     if (base >= nbytes) return;  // wave-uniform
     const uint32_t lane_off = (threadIdx.x % kWave) * 16u;
-    // bytes of this chunk that exist (16384 for every chunk but the last)
+    // Bytes of this chunk that exist: 16384 except in the last chunk.  The
+    // chunk is addressed through buffer resources sized to it, so the
+    // hardware range check zero-fills loads and drops stores past the end;
+    // the partial path uses 8-byte accesses, each wholly in or out of range.
     const uint32_t avail = (uint32_t)(nbytes - base < kChunk ? nbytes - base : kChunk);
-    const uint8_t *src = in + base;
-    uint8_t *dst = out + base;
+    const bool whole = VEC16 && avail == (uint32_t)kChunk;
+    const __amdgpu_buffer_rsrc_t src =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(in + base), 0, (int)avail, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t dst =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(out + base), 0, (int)avail, kBufferFlags);
 
     uint32_t h0[32], h1[32];
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        const uint32_t o = lane_off + k * 1024u;
-        uint2 a = make_uint2(0u, 0u), b = make_uint2(0u, 0u);
-        if (VEC16 && o + 16u <= avail) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(src + o);
-            a = make_uint2(v.x, v.y);
-            b = make_uint2(v.z, v.w);
-        } else {
-            if (o + 8u <= avail) a = *reinterpret_cast<const uint2 *>(src + o);
-            if (o + 16u <= avail) b = *reinterpret_cast<const uint2 *>(src + o + 8);
+        for (int k = 0; k < 16; k++) {
+            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(src, lane_off, k * 1024, 0);
+            h0[2 * k] = v[0];
+            h1[2 * k] = v[1];
+            h0[2 * k + 1] = v[2];
+            h1[2 * k + 1] = v[3];
         }
-        h0[2 * k] = a.x;
-        h1[2 * k] = a.y;
-        h0[2 * k + 1] = b.x;
-        h1[2 * k + 1] = b.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const v2u a = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off, k * 1024, 0);
+            const v2u b = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off + 8u, k * 1024, 0);
+            h0[2 * k] = a[0];
+            h1[2 * k] = a[1];
+            h0[2 * k + 1] = b[0];
+            h1[2 * k + 1] = b[1];
+        }
     }
     transpose32(h0);
     transpose32(h1);
@@ -148,16 +168,18 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     transpose32(h0);
     transpose32(h1);
 
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        const uint32_t o = lane_off + k * 1024u;
-        if (VEC16 && o + 16u <= avail) {
-            *reinterpret_cast<uint4 *>(dst + o) =
-                make_uint4(h0[2 * k], h1[2 * k], h0[2 * k + 1], h1[2 * k + 1]);
-        } else {
-            if (o + 8u <= avail) *reinterpret_cast<uint2 *>(dst + o) = make_uint2(h0[2 * k], h1[2 * k]);
-            if (o + 16u <= avail)
-                *reinterpret_cast<uint2 *>(dst + o + 8) = make_uint2(h0[2 * k + 1], h1[2 * k + 1]);
+        for (int k = 0; k < 16; k++) {
+            const v4u v = {h0[2 * k], h1[2 * k], h0[2 * k + 1], h1[2 * k + 1]};
+            __builtin_amdgcn_raw_buffer_store_b128(v, dst, lane_off, k * 1024, 0);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const v2u a = {h0[2 * k], h1[2 * k]}, b = {h0[2 * k + 1], h1[2 * k + 1]};
+            __builtin_amdgcn_raw_buffer_store_b64(a, dst, lane_off, k * 1024, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(b, dst, lane_off + 8u, k * 1024, 0);
         }
     }
 }

@@ -123,6 +123,9 @@ static int cost_est(const Net &n, u64 t, u64 care) {
     return 3;
 }
 
+static int g_lookahead = 0;
+static Ref split_join(Net &n, u64 t, u64 care, int sel, int first_side, int depth);
+
 static Ref solve(Net &n, u64 t, u64 care, int depth) {
     if (!care) return {-1, 0};
     Ref r;
@@ -143,8 +146,31 @@ static Ref solve(Net &n, u64 t, u64 care, int depth) {
         if (sc == best_sc) best.push_back(s);
     }
     int sel = best[rng() % best.size()];
-    u64 S = n.tt[sel];
     int first_side = (int)(rng() & 1);
+    if (depth < g_lookahead && best.size() > 1) {
+        // try every tied selector and both sides on copies; keep the cheapest
+        size_t best_gates = (size_t)-1;
+        Net best_net;
+        Ref best_ref = {-1, 0};
+        for (int cand : best) {
+            for (int side = 0; side < 2; side++) {
+                Net c = n;
+                Ref r2 = split_join(c, t, care, cand, side, depth);
+                if (c.g.size() < best_gates) {
+                    best_gates = c.g.size();
+                    best_net = c;
+                    best_ref = r2;
+                }
+            }
+        }
+        n = best_net;
+        return best_ref;
+    }
+    return split_join(n, t, care, sel, first_side, depth);
+}
+
+static Ref split_join(Net &n, u64 t, u64 care, int sel, int first_side, int depth) {
+    u64 S = n.tt[sel];
     u64 care_first = care & (first_side ? S : ~S);
     u64 care_second = care & (first_side ? ~S : S);
 
@@ -216,9 +242,10 @@ static Net prune(const Net &n) {
 
 int main(int argc, char **argv) {
     if (argc != 4 + 63) {
-        fprintf(stderr, "usage: %s restarts seed v0 .. v63\n", argv[0]);
+        fprintf(stderr, "usage: %s restarts seed v0 .. v63   (env SBOX_LOOKAHEAD=depth)\n", argv[0]);
         return 1;
     }
+    if (getenv("SBOX_LOOKAHEAD")) g_lookahead = atoi(getenv("SBOX_LOOKAHEAD"));
     int restarts = atoi(argv[1]);
     rng.seed(strtoull(argv[2], 0, 0));
     int box[64];

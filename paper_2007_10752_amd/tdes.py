@@ -9,7 +9,8 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libtdes.so")
+# TDES_LIB names another build of the same library (for comparing builds).
+LIB_PATH = os.environ.get("TDES_LIB") or os.path.join(PKG, "libtdes.so")
 
 ENCRYPT, DECRYPT = 0, 1
 KERNEL_AUTO, KERNEL_BITSLICE, KERNEL_SPBOX = 0, 1, 2

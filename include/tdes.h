@@ -88,6 +88,50 @@ tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_
 tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const void *d_in,
                            void *d_out, size_t nbytes, void *stream);
 
+/* ---- Batched form: many messages, each with its own key and direction --- */
+
+/* Bytes of device-resident key material per schedule (both directions). */
+#define TDES_DEVICE_SCHEDULE_BYTES 800
+
+/* One message of a batch (device memory, 32 bytes).  The message is nbytes
+ * bytes (a multiple of 8) at byte offset in_off of the batch's input base
+ * and its result goes to out_off of the output base (both multiples of 8;
+ * in_off == out_off on the same base is in place).  It is encrypted or
+ * decrypted (dir) with schedule sched_idx of the batch's device schedules.
+ * Messages must not overlap each other's outputs. */
+typedef struct {
+    uint64_t in_off;
+    uint64_t out_off;
+    uint64_t nbytes;
+    uint32_t sched_idx;
+    uint32_t dir;
+} tdes_msg;
+
+/* Write the device-resident key material of n schedules (host memory h) to
+ * d_dst (device, n * TDES_DEVICE_SCHEDULE_BYTES bytes, 16-byte aligned,
+ * owned by the caller).  The copy is enqueued on `stream` and waited for:
+ * h may be reused on return.  Errors: TDES_ERR_ARG, TDES_ERR_ALIGN,
+ * TDES_ERR_DEVICE. */
+tdes_status tdes_schedule_upload(const tdes_schedule *h, size_t n, void *d_dst, void *stream);
+
+/* Device workspace bytes tdes_batch_submit needs for n_msgs messages. */
+size_t tdes_batch_workspace_bytes(size_t n_msgs);
+
+/* 3DES-EDE ECB over a batch of messages in one pass (the batched form of
+ * tdes_ecb_crypt: per-message keys and directions, Sec. III-B; ECB, Sec. V).
+ * d_msgs: n_msgs descriptors in device memory; d_schedules: n_schedules
+ * entries written by tdes_schedule_upload; d_in_base / d_out_base: device
+ * bases the message offsets refer to (8-byte aligned); d_workspace:
+ * tdes_batch_workspace_bytes(n_msgs) bytes of device memory (8-byte aligned),
+ * overwritten.  Asynchronous on `stream`.  Message fields are checked on the
+ * device: a message with a bad length, offset, schedule index or direction
+ * is skipped, and the number skipped is left in the second 64-bit word of
+ * the workspace.  Errors (synchronous): TDES_ERR_ARG (NULL pointers with
+ * n_msgs > 0, workspace too small), TDES_ERR_ALIGN, TDES_ERR_DEVICE. */
+tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                              size_t n_schedules, const void *d_in_base, void *d_out_base,
+                              void *d_workspace, size_t workspace_bytes, void *stream);
+
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
  * TDES_KERNEL_SPBOX; AUTO means the kernel AUTO selects) would receive for
  * schedule ks and direction dir, copied to host memory `out` (cap bytes).

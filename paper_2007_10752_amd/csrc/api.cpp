@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -83,6 +84,48 @@ tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_
 tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
                              size_t nbytes, void *stream) {
     return tdes_ecb_crypt(ks, TDES_DECRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);
+}
+
+tdes_status tdes_schedule_upload(const tdes_schedule *h, size_t n, void *d_dst, void *stream) {
+    g_last_error.clear();
+    if (n == 0) return TDES_OK;
+    if (h == nullptr || d_dst == nullptr) return fail(TDES_ERR_ARG, "NULL schedules or destination");
+    if ((uintptr_t)d_dst % 16 != 0) return fail(TDES_ERR_ALIGN, "destination must be 16-byte aligned");
+    std::vector<uint32_t> words(n * tdes::kDeviceScheduleWords);
+    for (size_t i = 0; i < n; i++)
+        tdes::device_schedule_words(h[i], words.data() + i * tdes::kDeviceScheduleWords);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(d_dst, words.data(), words.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "schedule upload failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
+size_t tdes_batch_workspace_bytes(size_t n_msgs) { return tdes::batch_workspace_bytes(n_msgs); }
+
+tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                              size_t n_schedules, const void *d_in_base, void *d_out_base,
+                              void *d_workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    if (n_msgs == 0) return TDES_OK;
+    if (d_msgs == nullptr || d_schedules == nullptr || d_in_base == nullptr ||
+        d_out_base == nullptr || d_workspace == nullptr)
+        return fail(TDES_ERR_ARG, "NULL pointer");
+    if (n_schedules == 0) return fail(TDES_ERR_ARG, "no schedules");
+    if (workspace_bytes < tdes::batch_workspace_bytes(n_msgs))
+        return fail(TDES_ERR_ARG, "workspace too small (%zu < %zu bytes)", workspace_bytes,
+                    tdes::batch_workspace_bytes(n_msgs));
+    if (((uintptr_t)d_msgs | (uintptr_t)d_in_base | (uintptr_t)d_out_base |
+         (uintptr_t)d_workspace) % 8 != 0 || (uintptr_t)d_schedules % 16 != 0)
+        return fail(TDES_ERR_ALIGN, "misaligned pointer");
+    hipError_t e = tdes::launch_batch(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
+                                      n_schedules, static_cast<const uint8_t *>(d_in_base),
+                                      static_cast<uint8_t *>(d_out_base),
+                                      static_cast<uint64_t *>(d_workspace),
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
+    return TDES_OK;
 }
 
 long tdes_kernel_key_bytes(const tdes_schedule *ks, int dir, int kernel, void *out, size_t cap) {

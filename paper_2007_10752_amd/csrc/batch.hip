@@ -1,0 +1,172 @@
+// Batched 3DES-EDE ECB: many messages of uneven length, each with its own
+// key schedule and direction, in one pass over the device.
+//
+// Work unit: a lane slice of 256 bytes (32 blocks) of one message; a
+// message of n bytes has ceil(n / 256) slices.  A single-workgroup scan
+// turns the descriptors into first-slice offsets (in the caller's
+// workspace); then a persistent grid sized to the resident waves walks the
+// slices, one per lane, 64 consecutive slices per wave per step.  Each lane
+// finds its message (the wave binary-searches the message of its first
+// slice with scalar loads, each lane walks forward from it), loads its 256
+// bytes, and runs the same bitsliced core as the plain kernel, with its
+// message's key masks: two mask words per round read from the device
+// schedule table (cached; identical across lanes of one message) and
+// expanded bit by bit with v_bfe_i32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bitslice_core.h"
+#include "internal.h"
+
+#ifndef TDES_BATCH_MIN_WAVES
+#define TDES_BATCH_MIN_WAVES 3
+#endif
+
+namespace tdes {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kThreads = kWave * kWavesPerBlock;
+constexpr uint32_t kSlice = 256;  // bytes per lane
+constexpr int kScanThreads = 1024;
+
+// Workspace words: [0] total slices, [1] skipped messages,
+// [2 + i] first slice of message i (i = 0..n; entry n = total).
+constexpr int kWsHeader = 2;
+
+__device__ __forceinline__ uint64_t slices_of(const tdes_msg &m, size_t n_sched, bool *bad) {
+    const bool ok = (m.nbytes % 8 == 0) && (m.in_off % 8 == 0) && (m.out_off % 8 == 0) &&
+                    (m.sched_idx < n_sched) && (m.dir <= 1);
+    *bad = !ok;
+    return ok ? (m.nbytes + kSlice - 1) / kSlice : 0;
+}
+
+__global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg *msgs, size_t n,
+                                                                 size_t n_sched, uint64_t *ws) {
+    __shared__ uint64_t part[kScanThreads];
+    __shared__ uint32_t nbad[kScanThreads];
+    const size_t per = (n + kScanThreads - 1) / kScanThreads;
+    const size_t lo = min(n, (size_t)threadIdx.x * per), hi = min(n, lo + per);
+    uint64_t sum = 0;
+    uint32_t bad_count = 0;
+    for (size_t i = lo; i < hi; i++) {
+        bool bad;
+        sum += slices_of(msgs[i], n_sched, &bad);
+        bad_count += bad;
+    }
+    part[threadIdx.x] = sum;
+    nbad[threadIdx.x] = bad_count;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive scan
+        const uint64_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
+        const uint32_t b = threadIdx.x >= (unsigned)d ? nbad[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        nbad[threadIdx.x] += b;
+        __syncthreads();
+    }
+    uint64_t run = part[threadIdx.x] - sum;
+    for (size_t i = lo; i < hi; i++) {
+        ws[kWsHeader + i] = run;
+        bool bad;
+        run += slices_of(msgs[i], n_sched, &bad);
+    }
+    if (threadIdx.x == kScanThreads - 1) {
+        ws[0] = part[kScanThreads - 1];
+        ws[1] = nbad[kScanThreads - 1];
+        ws[kWsHeader + n] = part[kScanThreads - 1];
+    }
+}
+
+// Round masks expanded from a lane's own mask words.
+struct LaneMasks {
+    uint32_t lo, hi;  // 32 output-XOR mask bits, 16 second-use mask bits
+    __device__ __forceinline__ uint32_t operator()(int i) const {
+        return (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? lo : hi), i < 32 ? i : i - 32, 1);
+    }
+};
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TDES_BATCH_MIN_WAVES, 8)))
+void batch_bitslice_kernel(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sched,
+                           size_t n_sched, const uint8_t *in, uint8_t *out, const uint64_t *ws) {
+    const uint64_t total = ws[0];
+    const uint64_t *first = ws + kWsHeader;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t base = ((uint64_t)blockIdx.x * kWavesPerBlock + wave) * kWave; base < total;
+         base += stride) {
+        // message holding slice `base`: largest m with first[m] <= base
+        size_t lo = 0, hi = n_msgs;
+        while (hi - lo > 1) {
+            const size_t mid = (lo + hi) / 2;
+            if (first[mid] <= base) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t s = base + lane;
+        const bool active = s < total;
+        size_t m = lo;
+        if (active)
+            while (first[m + 1] <= s) m++;
+        const tdes_msg d = msgs[m];
+        const uint64_t off = (s - first[m]) * kSlice;
+        const uint32_t nb = active ? (uint32_t)min((uint64_t)kSlice, d.nbytes - off) : 0u;
+        const uint8_t *src = in + d.in_off + off;
+        uint8_t *dst = out + d.out_off + off;
+        const uint32_t sidx = d.sched_idx < n_sched ? d.sched_idx : 0u;
+        const uint32_t *kw = sched + (size_t)sidx * kDeviceScheduleWords + (d.dir & 1u) * kDirWords;
+
+        uint32_t h0[32], h1[32];
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            uint2 v = make_uint2(0u, 0u);
+            if ((uint32_t)k * 8u < nb) v = *reinterpret_cast<const uint2 *>(src + 8 * k);
+            h0[k] = v.x;
+            h1[k] = v.y;
+        }
+        transpose32(h0);
+        transpose32(h1);
+        des3_planes(
+            h0, h1, [kw](int t) { return LaneMasks{kw[2 * t], kw[2 * t + 1]}; },
+            [kw](int g, int i) { return (uint32_t)__builtin_amdgcn_sbfe((int)kw[96 + g], i, 1); });
+        transpose32(h0);
+        transpose32(h1);
+#pragma unroll
+        for (int k = 0; k < 32; k++)
+            if ((uint32_t)k * 8u < nb)
+                *reinterpret_cast<uint2 *>(dst + 8 * k) = make_uint2(h0[k], h1[k]);
+    }
+}
+
+int resident_blocks() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        n = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock;  // 4 SIMDs per CU
+    }
+    return n;
+}
+
+}  // namespace
+
+size_t batch_workspace_bytes(size_t n_msgs) { return (kWsHeader + n_msgs + 1) * sizeof(uint64_t); }
+
+hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
+                        size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
+                        hipStream_t stream) {
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, msgs, n_msgs,
+                       n_schedules, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(resident_blocks()), dim3(kThreads), 0, stream,
+                       msgs, n_msgs, schedules, n_schedules, in, out, ws);
+    return hipGetLastError();
+}
+
+}  // namespace tdes

@@ -24,7 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "generated/bitslice_gen.h"
+#include "bitslice_core.h"
 #include "generated/bitslice_keys_gen.h"
 #include "internal.h"
 
@@ -44,36 +44,11 @@ constexpr int kBufferFlags = 0x00020000;
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
-// One swap-move stage of the 32x32 transpose: rows i and i+J (i & J == 0)
-// exchange the J-bit groups where row bit J differs from column bit J.
-template <int J>
-__device__ __forceinline__ void swap_stage(uint32_t (&x)[32]) {
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & J) continue;
-        const uint32_t a = x[i], b = x[i + J];
-        if (J == 16) {
-            x[i] = __builtin_amdgcn_perm(b, a, 0x05040100u);
-            x[i + J] = __builtin_amdgcn_perm(b, a, 0x07060302u);
-        } else if (J == 8) {
-            x[i] = __builtin_amdgcn_perm(b, a, 0x06020400u);
-            x[i + J] = __builtin_amdgcn_perm(b, a, 0x07030501u);
-        } else {
-            constexpr uint32_t m = J == 4 ? 0x0F0F0F0Fu : J == 2 ? 0x33333333u : 0x55555555u;
-            x[i] = (a & m) | ((b << J) & ~m);
-            x[i + J] = ((a >> J) & m) | (b & ~m);
-        }
-    }
-}
-
-// Exact transpose: afterwards bit b of x[p] is the old bit p of x[b].
-__device__ __forceinline__ void transpose32(uint32_t (&x)[32]) {
-    swap_stage<16>(x);
-    swap_stage<8>(x);
-    swap_stage<4>(x);
-    swap_stage<2>(x);
-    swap_stage<1>(x);
-}
+// Round masks read from LDS (uniform address: broadcast to the wave).
+struct LdsMasks {
+    const uint32_t *p;
+    __device__ __forceinline__ uint32_t operator()(int i) const { return p[i]; }
+};
 
 template <bool VEC16>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
@@ -128,43 +103,15 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     transpose32(h0);
     transpose32(h1);
 
-    uint32_t X[32], Y[32];
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        X[i] = BS_IP_L[i] < 32 ? h0[BS_IP_L[i]] : h1[BS_IP_L[i] - 32];
-        Y[i] = (BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32]) ^ km[kBsInitY + i];
-    }
-
-    // Pass 1 (L = X, R = Y); ends with X = L16, Y = R16.
-#pragma unroll 1
-    for (int r = 0; r < 16; r += 2) {
-        bs_round(X, Y, km + kBsRoundMasks * r);
-        bs_round(Y, X, km + kBsRoundMasks * (r + 1));
-    }
-    // Pass 2 starts from R16 || L16 of pass 1: L = Y, R = X.
-#pragma unroll
-    for (int i = 0; i < 32; i++) X[i] ^= km[kBsRemask16 + i];
-#pragma unroll 1
-    for (int r = 16; r < 32; r += 2) {
-        bs_round(Y, X, km + kBsRoundMasks * r);
-        bs_round(X, Y, km + kBsRoundMasks * (r + 1));
-    }
-    // Pass 3: L = X, R = Y again; ends with X = L16, Y = R16.
-#pragma unroll
-    for (int i = 0; i < 32; i++) Y[i] ^= km[kBsRemask32 + i];
-#pragma unroll 1
-    for (int r = 32; r < 48; r += 2) {
-        bs_round(X, Y, km + kBsRoundMasks * r);
-        bs_round(Y, X, km + kBsRoundMasks * (r + 1));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) X[i] ^= km[kBsFinalX + i];
-
-#pragma unroll
-    for (int q = 0; q < 32; q++) {
-        h0[q] = BS_FP_SRC[q] < 32 ? Y[BS_FP_SRC[q]] : X[BS_FP_SRC[q] - 32];
-        h1[q] = BS_FP_SRC[32 + q] < 32 ? Y[BS_FP_SRC[32 + q]] : X[BS_FP_SRC[32 + q] - 32];
-    }
+    const uint32_t *kml = km;
+    des3_planes(
+        h0, h1, [kml](int t) { return LdsMasks{kml + kBsRoundMasks * t}; },
+        [kml](int g, int i) {
+            return kml[(g == kGroupInitY     ? kBsInitY
+                        : g == kGroupRemask16 ? kBsRemask16
+                        : g == kGroupRemask32 ? kBsRemask32
+                                              : kBsFinalX) + i];
+        });
     transpose32(h0);
     transpose32(h1);
 

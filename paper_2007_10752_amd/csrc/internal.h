@@ -29,7 +29,16 @@ struct SpboxKeys {
     uint32_t ke[48], ko[48], k0[48], k7[48];
 };
 
+// Device-resident key material of one schedule (tdes_schedule_upload):
+// for each direction, 100 words: [2t] the 32 output-XOR mask bits of round
+// t, [2t+1] its 16 second-use mask bits, [96..99] the initial mask of R, the
+// re-masks before rounds 16 and 32 and the final unmask of X (32 bits each).
+constexpr int kDirWords = 100;
+constexpr int kDeviceScheduleWords = 2 * kDirWords;
+static_assert(kDeviceScheduleWords * 4 == TDES_DEVICE_SCHEDULE_BYTES, "schedule size");
+
 void des_round_keys(const uint8_t key[8], uint64_t rk[16]);
+void device_schedule_words(const tdes_schedule &ks, uint32_t out[kDeviceScheduleWords]);
 void round_sequence(const tdes_schedule &ks, int dir, RoundSequence *seq);
 void bitslice_keys(const RoundSequence &seq, BitsliceKeys *out);
 void spbox_keys(const RoundSequence &seq, SpboxKeys *out);
@@ -37,6 +46,10 @@ void spbox_keys(const RoundSequence &seq, SpboxKeys *out);
 // Launchers: enqueue on `stream`; return the HIP launch status.
 hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *out,
                            size_t nbytes, hipStream_t stream);
+size_t batch_workspace_bytes(size_t n_msgs);
+hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
+                        size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
+                        hipStream_t stream);
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 

@@ -96,6 +96,25 @@ void bitslice_keys(const RoundSequence &seq, BitsliceKeys *out) {
     for (int i = 0; i < 32; i++) put(kBsFinalX + i, mx[i]);
 }
 
+static uint32_t mask_bit(const BitsliceKeys &k, int i) { return (k.bits[i / 32] >> (i % 32)) & 1u; }
+
+void device_schedule_words(const tdes_schedule &ks, uint32_t out[kDeviceScheduleWords]) {
+    memset(out, 0, kDeviceScheduleWords * sizeof(uint32_t));
+    for (int dir = 0; dir < 2; dir++) {
+        RoundSequence seq;
+        BitsliceKeys k;
+        round_sequence(ks, dir, &seq);
+        bitslice_keys(seq, &k);
+        uint32_t *w = out + dir * kDirWords;
+        for (int t = 0; t < 48; t++)
+            for (int o = 0; o < 48; o++)
+                w[2 * t + o / 32] |= mask_bit(k, kBsRoundMasks * t + o) << (o % 32);
+        static const int kExtra[4] = {kBsInitY, kBsRemask16, kBsRemask32, kBsFinalX};
+        for (int g = 0; g < 4; g++)
+            for (int i = 0; i < 32; i++) w[96 + g] |= mask_bit(k, kExtra[g] + i) << i;
+    }
+}
+
 // Key chunk s (bits 6s+1..6s+6 of the round key) lines up with S-box window
 // s of the right half R (bit i of R at position 32 - i):
 //   windows 1..6 sit at positions 27-4s .. 32-4s of R; odd and even windows

@@ -22,7 +22,11 @@ STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR
 # Exported symbols, checked against include/*.h by the tests.
 SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
            "tdes_last_error", "tdes_abi_version", "tdes_kernel_key_bytes", "tdes_probe_valu",
-           "tdes_probe_copy")
+           "tdes_probe_copy", "tdes_schedule_upload", "tdes_batch_workspace_bytes",
+           "tdes_batch_submit")
+
+DEVICE_SCHEDULE_BYTES = 800
+MSG_BYTES = 32
 
 
 class TdesError(RuntimeError):
@@ -64,6 +68,12 @@ def lib():
         L.tdes_last_error.restype = ctypes.c_char_p
         L.tdes_abi_version.argtypes = []
         L.tdes_abi_version.restype = ctypes.c_int
+        L.tdes_schedule_upload.argtypes = [sched_p, sz, vp, vp]
+        L.tdes_schedule_upload.restype = ctypes.c_int
+        L.tdes_batch_workspace_bytes.argtypes = [sz]
+        L.tdes_batch_workspace_bytes.restype = sz
+        L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp]
+        L.tdes_batch_submit.restype = ctypes.c_int
         L.tdes_kernel_key_bytes.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, sz]
         L.tdes_kernel_key_bytes.restype = ctypes.c_long
         L.tdes_probe_valu.argtypes = [ctypes.c_int, vp, ctypes.c_uint, ctypes.c_uint, vp]
@@ -142,3 +152,81 @@ def encrypt(key, x, out=None, kernel="auto", stream=None):
 
 def decrypt(key, x, out=None, kernel="auto", stream=None):
     return ecb(key, x, out, True, kernel, stream)
+
+
+# ---- batched form -----------------------------------------------------------
+
+def key_schedules(keys):
+    """Schedules of many 24-byte bundles (array-like of shape (n, 24)), as a
+    ctypes array of tdes_schedule."""
+    import numpy as np
+    k = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 24)
+    arr = (Schedule * len(k))()
+    buf = (ctypes.c_uint8 * 24)()
+    L = lib()
+    for i in range(len(k)):
+        ctypes.memmove(buf, k[i].ctypes.data, 24)
+        _check(L.tdes_key_schedule(buf, ctypes.byref(arr[i])))
+    return arr
+
+
+def schedule_upload(schedules, d_dst, stream=0):
+    """tdes_schedule_upload of a ctypes array of Schedule to device address d_dst."""
+    _check(lib().tdes_schedule_upload(schedules, len(schedules), ctypes.c_void_p(d_dst),
+                                      ctypes.c_void_p(stream)))
+
+
+def batch_workspace_bytes(n_msgs):
+    return int(lib().tdes_batch_workspace_bytes(n_msgs))
+
+
+def batch_submit_ptr(d_msgs, n_msgs, d_sched, n_sched, d_in, d_out, d_ws, ws_bytes, stream=0):
+    """tdes_batch_submit on raw device addresses."""
+    _check(lib().tdes_batch_submit(ctypes.c_void_p(d_msgs), n_msgs, ctypes.c_void_p(d_sched),
+                                   n_sched, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                                   ctypes.c_void_p(d_ws), ws_bytes, ctypes.c_void_p(stream)))
+
+
+def msg_table(in_off, out_off, nbytes, sched_idx, dirs):
+    """Descriptor array (numpy, n x 4 int64 = n tdes_msg) from per-message fields."""
+    import numpy as np
+    n = len(nbytes)
+    t = np.zeros((n, 4), dtype=np.uint64)
+    t[:, 0] = np.asarray(in_off, dtype=np.uint64)
+    t[:, 1] = np.asarray(out_off, dtype=np.uint64)
+    t[:, 2] = np.asarray(nbytes, dtype=np.uint64)
+    t[:, 3] = (np.asarray(sched_idx, dtype=np.uint64) |
+               (np.asarray(dirs, dtype=np.uint64) << np.uint64(32)))
+    return t.view(np.int64)
+
+
+class Batch:
+    """Device-resident pieces of one batch: descriptors, key schedules and
+    workspace (torch tensors), built once and submitted any number of times."""
+
+    def __init__(self, keys, in_off, out_off, nbytes, dirs, sched_idx=None, stream=None):
+        import numpy as np
+        import torch
+        n = len(nbytes)
+        if sched_idx is None:
+            sched_idx = np.arange(n)
+        sch = key_schedules(keys)
+        self.n_msgs, self.n_sched = n, len(sch)
+        self.sched = torch.empty(len(sch) * DEVICE_SCHEDULE_BYTES, dtype=torch.uint8, device="cuda")
+        self.stream = _stream_handle(stream)
+        schedule_upload(sch, self.sched.data_ptr(), self.stream)
+        table = msg_table(in_off, out_off, nbytes, sched_idx, dirs)
+        self.msgs = torch.from_numpy(table).to("cuda")
+        self.ws_bytes = batch_workspace_bytes(n)
+        self.ws = torch.empty((self.ws_bytes + 7) // 8, dtype=torch.int64, device="cuda")
+
+    def submit(self, x, out, stream=None):
+        """Run the batch over input base x and output base out (uint8 CUDA tensors)."""
+        batch_submit_ptr(self.msgs.data_ptr(), self.n_msgs, self.sched.data_ptr(), self.n_sched,
+                         x.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                         _stream_handle(stream) if stream is not None else self.stream)
+        return out
+
+    def skipped(self):
+        """Messages the last submit skipped as invalid (synchronises)."""
+        return int(self.ws[1].item())

@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--input", default="uniform", choices=["uniform", "zero", "pattern"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the oracle sample (0 disables)")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the batched form (16,384 log-normal messages); 0 disables")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of the same size (for PMC scaling)")
     return ap.parse_args()
@@ -59,10 +61,64 @@ def cpu_baseline(key, host, target_s):
                       % (nblk, sample.size / 2**20, dt)}
 
 
+def time_launches(fn, reps, stream):
+    """Median wall time of `reps` calls of fn() between HIP events on stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def batched_section(steps):
+    """The batched form on 16,384 messages (log-normal lengths, median 4 KiB,
+    sigma 1, 8 B .. 1 MiB; own 3-key bundle each; 50/50 directions), against
+    the plain kernel over the same bytes with one key and against one plain
+    launch per message."""
+    import torch
+
+    from paper_2007_10752_amd import tdes
+    from paper_2007_10752_amd import workloads as W
+    lay = W.batched_layout(W.SEED_BASE + 3)
+    total = lay["total"]
+    data = W.uniform_bytes(W.rng(W.SEED_BASE + 3 + W.KEY_SEED_OFFSET), total)
+    x = torch.from_numpy(data).cuda()
+    out = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    b = tdes.Batch(lay["keys"], lay["offsets"], lay["offsets"], lay["lengths"], lay["dirs"])
+    t_batch = time_launches(lambda: b.submit(x, out), max(3, steps), stream)
+    sched = tdes.key_schedule(lay["keys"][0])
+    sh = int(stream.cuda_stream)
+    t_plain = time_launches(lambda: tdes.ecb_crypt_ptr(sched, 0, 1, x.data_ptr(), out.data_ptr(),
+                                                       total, sh), max(3, steps), stream)
+    scheds = tdes.key_schedules(lay["keys"])
+    offs, lens, dirs = lay["offsets"].tolist(), lay["lengths"].tolist(), lay["dirs"].tolist()
+    xb, ob = x.data_ptr(), out.data_ptr()
+
+    def per_message():
+        for i in range(len(lens)):
+            tdes.ecb_crypt_ptr(scheds[i], dirs[i], 1, xb + offs[i], ob + offs[i], lens[i], sh)
+
+    t_loop = time_launches(per_message, 1, stream)
+    return {"value": round(total / t_batch / 1e9, 3), "unit": "GB/s",
+            "ms": round(t_batch * 1e3, 4), "messages": len(lens), "bytes": total,
+            "plain_same_bytes_GBps": round(total / t_plain / 1e9, 3),
+            "per_message_launches_GBps": round(total / t_loop / 1e9, 3),
+            "config": "16384 msgs, lognormal median 4 KiB sigma 1, clip 8 B..1 MiB, "
+                      "per-message 3-key bundle, 50/50 enc/dec, seed %d" % (W.SEED_BASE + 3)}
+
+
 def traffic_from_profile(kernel, nbytes):
     """HBM bytes per launch from the committed PMC summary, if it was taken
     on the current kernel source and workload; else None."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "%s_1gib_pmc.md" % kernel)
     if not os.path.exists(path) or nbytes != GIB:
         return None
@@ -73,15 +129,23 @@ def traffic_from_profile(kernel, nbytes):
                 for kv in line.split(":", 1)[1].split():
                     k, v = kv.split("=")
                     fields[k] = v
-    src = os.path.join(ROOT, "paper_2007_10752_amd", "csrc", "%s.hip" % kernel)
-    gen = os.path.join(ROOT, "paper_2007_10752_amd", "csrc", "generated", "%s_gen.h" % kernel)
-    h = hashlib.sha256()
-    for p in (src, gen):
-        with open(p, "rb") as f:
-            h.update(f.read())
-    if fields.get("source_sha256") != h.hexdigest()[:16]:
+    if fields.get("source_sha256") != kernel_source_hash(kernel):
         return None
     return float(fields["bytes_per_launch"])
+
+
+def kernel_source_hash(kernel):
+    """Hash of the sources a kernel is compiled from (to tell whether stored
+    counter readings still describe it)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2007_10752_amd", "csrc")
+    files = {"bitslice": ["bitslice.hip", "bitslice_core.h", "generated/bitslice_gen.h"],
+             "spbox": ["spbox.hip", "generated/spbox_gen.h"]}[kernel]
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -179,6 +243,10 @@ def main():
                               / costs.HBM_PEAK_BYTES, 4),
         },
     }
+    if args.batched:
+        del x, out
+        line["batched"] = batched_section(args.steps)
+        print("batched done", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(key, host, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -87,6 +87,13 @@ struct LaneMasks {
         return (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? lo : hi), i < 32 ? i : i - 32, 1);
     }
 };
+struct LaneRounds {
+    const uint32_t *kw;  // this lane's 100 mask words (round t at 2t, 2t+1)
+    __device__ __forceinline__ uint2 load(int t) const {
+        return *reinterpret_cast<const uint2 *>(kw + 2 * t);
+    }
+    __device__ __forceinline__ LaneMasks masks(uint2 w) const { return LaneMasks{w.x, w.y}; }
+};
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TDES_BATCH_MIN_WAVES, 8)))
 void batch_bitslice_kernel(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sched,
@@ -129,7 +136,7 @@ void batch_bitslice_kernel(const tdes_msg *msgs, size_t n_msgs, const uint32_t *
         transpose32(h0);
         transpose32(h1);
         des3_planes(
-            h0, h1, [kw](int t) { return LaneMasks{kw[2 * t], kw[2 * t + 1]}; },
+            h0, h1, LaneRounds{kw},
             [kw](int g, int i) { return (uint32_t)__builtin_amdgcn_sbfe((int)kw[96 + g], i, 1); });
         transpose32(h0);
         transpose32(h1);

@@ -49,6 +49,11 @@ struct LdsMasks {
     const uint32_t *p;
     __device__ __forceinline__ uint32_t operator()(int i) const { return p[i]; }
 };
+struct LdsRounds {
+    const uint32_t *km;
+    __device__ __forceinline__ const uint32_t *load(int t) const { return km + kBsRoundMasks * t; }
+    __device__ __forceinline__ LdsMasks masks(const uint32_t *p) const { return LdsMasks{p}; }
+};
 
 template <bool VEC16>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
@@ -105,7 +110,7 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
 
     const uint32_t *kml = km;
     des3_planes(
-        h0, h1, [kml](int t) { return LdsMasks{kml + kBsRoundMasks * t}; },
+        h0, h1, LdsRounds{kml},
         [kml](int g, int i) {
             return kml[(g == kGroupInitY     ? kBsInitY
                         : g == kGroupRemask16 ? kBsRemask16

@@ -50,7 +50,9 @@ __device__ __forceinline__ void transpose32(uint32_t (&x)[32]) {
 enum { kGroupInitY = 0, kGroupRemask16 = 1, kGroupRemask32 = 2, kGroupFinalX = 3 };
 
 // 3DES-EDE on 32 blocks held as planes h0 (word 0) and h1 (word 1), in
-// place.  rm(t) gives the mask source of round t (see bs_round); em(g, i)
+// place.  Round masks come from `rm`: rm.load(t) fetches what round t needs
+// (issued two rounds ahead, so memory latency overlaps the rounds before)
+// and rm.masks(v) turns it into the mask source bs_round reads.  em(g, i)
 // gives mask i of extra group g.
 template <class RoundMasks, class ExtraMasks>
 __device__ __forceinline__ void des3_planes(uint32_t (&h0)[32], uint32_t (&h1)[32],
@@ -61,27 +63,37 @@ __device__ __forceinline__ void des3_planes(uint32_t (&h0)[32], uint32_t (&h1)[3
         X[i] = BS_IP_L[i] < 32 ? h0[BS_IP_L[i]] : h1[BS_IP_L[i] - 32];
         Y[i] = (BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32]) ^ em(kGroupInitY, i);
     }
+    auto a = rm.load(0), b = rm.load(1);
     // Pass 1 (L = X, R = Y); ends with X = L16, Y = R16.
 #pragma unroll 1
     for (int r = 0; r < 16; r += 2) {
-        bs_round(X, Y, rm(r));
-        bs_round(Y, X, rm(r + 1));
+        const auto na = rm.load(r + 2), nb = rm.load(r + 3);
+        bs_round(X, Y, rm.masks(a));
+        bs_round(Y, X, rm.masks(b));
+        a = na;
+        b = nb;
     }
     // Pass 2 starts from R16 || L16 of pass 1: L = Y, R = X.
 #pragma unroll
     for (int i = 0; i < 32; i++) X[i] ^= em(kGroupRemask16, i);
 #pragma unroll 1
     for (int r = 16; r < 32; r += 2) {
-        bs_round(Y, X, rm(r));
-        bs_round(X, Y, rm(r + 1));
+        const auto na = rm.load(r + 2), nb = rm.load(r + 3);
+        bs_round(Y, X, rm.masks(a));
+        bs_round(X, Y, rm.masks(b));
+        a = na;
+        b = nb;
     }
     // Pass 3: L = X, R = Y again; ends with X = L16, Y = R16.
 #pragma unroll
     for (int i = 0; i < 32; i++) Y[i] ^= em(kGroupRemask32, i);
 #pragma unroll 1
     for (int r = 32; r < 48; r += 2) {
-        bs_round(X, Y, rm(r));
-        bs_round(Y, X, rm(r + 1));
+        const auto na = rm.load(r + 2), nb = rm.load(r + 3);  // 48, 49: harmless, unused
+        bs_round(X, Y, rm.masks(a));
+        bs_round(Y, X, rm.masks(b));
+        a = na;
+        b = nb;
     }
 #pragma unroll
     for (int i = 0; i < 32; i++) X[i] ^= em(kGroupFinalX, i);

@@ -114,6 +114,15 @@ typedef struct {
  * TDES_ERR_DEVICE. */
 tdes_status tdes_schedule_upload(const tdes_schedule *h, size_t n, void *d_dst, void *stream);
 
+/* The key generation of Sec. III-A on the device, for many bundles at once
+ * (the role of the paper's key-generation kernel, Sec. IV-A, applied to a
+ * whole batch): n key bundles of 24 bytes (K1 || K2 || K3) at d_keys24
+ * (device) become n device-resident schedules at d_schedules (device,
+ * n * TDES_DEVICE_SCHEDULE_BYTES bytes, 16-byte aligned), the same bytes
+ * tdes_schedule_upload writes.  Asynchronous on `stream`.  Errors:
+ * TDES_ERR_ARG, TDES_ERR_ALIGN, TDES_ERR_DEVICE. */
+tdes_status tdes_schedule_expand(const void *d_keys24, size_t n, void *d_schedules, void *stream);
+
 /* Device workspace bytes tdes_batch_submit needs for n_msgs messages. */
 size_t tdes_batch_workspace_bytes(size_t n_msgs);
 

@@ -43,7 +43,7 @@ extern "C" {
 tdes_status tdes_key_schedule(const uint8_t key24[24], tdes_schedule *out) {
     g_last_error.clear();
     if (key24 == nullptr || out == nullptr) return fail(TDES_ERR_ARG, "NULL key or schedule");
-    for (int b = 0; b < 3; b++) tdes::des_round_keys(key24 + 8 * b, out->k[b]);
+    for (int b = 0; b < 3; b++) tdes::des_round_keys(key24 + 8 * b, out->k[b]);  // Sec. III-A
     return TDES_OK;
 }
 
@@ -69,7 +69,7 @@ tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const v
         e = tdes::launch_spbox(k, in, out, nbytes, s);
     } else {
         tdes::BitsliceKeys k;
-        tdes::bitslice_keys(seq, &k);
+        tdes::bitslice_keys(*ks, dir, &k);
         e = tdes::launch_bitslice(k, in, out, nbytes, s);
     }
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -99,6 +99,18 @@ tdes_status tdes_schedule_upload(const tdes_schedule *h, size_t n, void *d_dst, 
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "schedule upload failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
+tdes_status tdes_schedule_expand(const void *d_keys24, size_t n, void *d_schedules, void *stream) {
+    g_last_error.clear();
+    if (n == 0) return TDES_OK;
+    if (d_keys24 == nullptr || d_schedules == nullptr) return fail(TDES_ERR_ARG, "NULL pointer");
+    if ((uintptr_t)d_schedules % 16 != 0) return fail(TDES_ERR_ALIGN, "schedules must be 16-byte aligned");
+    hipError_t e = tdes::launch_expand(static_cast<const uint8_t *>(d_keys24), n,
+                                       static_cast<uint32_t *>(d_schedules),
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "expand launch failed: %s", hipGetErrorString(e));
     return TDES_OK;
 }
 
@@ -145,7 +157,7 @@ long tdes_kernel_key_bytes(const tdes_schedule *ks, int dir, int kernel, void *o
     }
     tdes::BitsliceKeys k;
     if (cap < sizeof k) return fail(TDES_ERR_ARG, "buffer too small (%zu < %zu)", cap, sizeof k);
-    tdes::bitslice_keys(seq, &k);
+    tdes::bitslice_keys(*ks, dir, &k);
     memcpy(out, &k, sizeof k);
     return (long)sizeof k;
 }

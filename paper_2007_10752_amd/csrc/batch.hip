@@ -147,6 +147,21 @@ void batch_bitslice_kernel(const tdes_msg *msgs, size_t n_msgs, const uint32_t *
     }
 }
 
+// One thread per (bundle, direction): the three key schedules, then the
+// 100 mask words of that direction.
+__global__ __launch_bounds__(256) void expand_kernel(const uint8_t *keys24, size_t n,
+                                                    uint32_t *schedules) {
+    const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= 2 * n) return;
+    const size_t b = g / 2;
+    const int dir = (int)(g % 2);
+    uint8_t key[24];
+    for (int i = 0; i < 24; i++) key[i] = keys24[24 * b + i];
+    uint64_t k[3][16];
+    for (int j = 0; j < 3; j++) des_round_keys(key + 8 * j, k[j]);
+    bitslice_mask_words(k, dir, schedules + b * kDeviceScheduleWords + dir * kDirWords);
+}
+
 int resident_blocks() {
     static int n = 0;
     if (n == 0) {
@@ -161,6 +176,14 @@ int resident_blocks() {
 }
 
 }  // namespace
+
+hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream) {
+    const size_t threads = 2 * n, blocks = (threads + 255) / 256;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, keys24, n,
+                       schedules);
+    return hipGetLastError();
+}
 
 size_t batch_workspace_bytes(size_t n_msgs) { return (kWsHeader + n_msgs + 1) * sizeof(uint64_t); }
 

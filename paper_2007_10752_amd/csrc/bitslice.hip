@@ -62,8 +62,13 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     // back with a uniform address they are broadcast to every lane and enter
     // the VALU as vector operands (full issue rate; a scalar operand halves it).
     __shared__ __align__(16) uint32_t km[kBsNumMasks];
-    for (int i = threadIdx.x; i < kBsNumMasks; i += kWave * kWavesPerBlock)
-        km[i] = 0u - ((keys.bits[i / 32] >> (i % 32)) & 1u);
+    for (int i = threadIdx.x; i < kBsNumMasks; i += kWave * kWavesPerBlock) {
+        // LDS index 48t + o <- bit o % 32 of word 2t + o / 32; 2304 + 32g + j <- bit j of word 96 + g
+        const int t = i / kBsRoundMasks, o = i % kBsRoundMasks;
+        const int word = i < kBsInitY ? 2 * t + o / 32 : 96 + (i - kBsInitY) / 32;
+        const int bit = i < kBsInitY ? o % 32 : (i - kBsInitY) % 32;
+        km[i] = 0u - ((keys.w[word] >> bit) & 1u);
+    }
     __syncthreads();
 
     // the wave index is uniform within the wave; say so, so the chunk base

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "keysched_core.h"
 #include "tdes.h"
 
 namespace tdes {
@@ -15,12 +16,11 @@ struct RoundSequence {
     uint64_t rk[48];  // 48-bit round keys, bit 1 = bit 47
 };
 
-// Kernel argument for the bitsliced kernel: the key masks of one launch
-// as bits (mask i is bit i % 32 of bits[i / 32]; layout in
-// generated/bitslice_keys_gen.h); the kernel expands them to 0 / ~0 words.
-constexpr int kBitsliceMaskWords = 76;
+// Kernel argument for the bitsliced kernel: the 100 key-mask words of one
+// direction (layout in keysched_core.h); the kernel expands the bits to
+// 0 / ~0 words in LDS.
 struct BitsliceKeys {
-    uint32_t bits[kBitsliceMaskWords];
+    uint32_t w[100];
 };
 
 // Kernel argument for the table kernel: per round, the key chunks XORed into
@@ -29,24 +29,22 @@ struct SpboxKeys {
     uint32_t ke[48], ko[48], k0[48], k7[48];
 };
 
-// Device-resident key material of one schedule (tdes_schedule_upload):
-// for each direction, 100 words: [2t] the 32 output-XOR mask bits of round
-// t, [2t+1] its 16 second-use mask bits, [96..99] the initial mask of R, the
-// re-masks before rounds 16 and 32 and the final unmask of X (32 bits each).
-constexpr int kDirWords = 100;
-constexpr int kDeviceScheduleWords = 2 * kDirWords;
+// Device-resident key material of one schedule (tdes_schedule_upload,
+// tdes_schedule_expand): the 100 mask words (keysched_core.h) of
+// encryption, then those of decryption.
+constexpr int kDeviceScheduleWords = 200;
 static_assert(kDeviceScheduleWords * 4 == TDES_DEVICE_SCHEDULE_BYTES, "schedule size");
 
-void des_round_keys(const uint8_t key[8], uint64_t rk[16]);
 void device_schedule_words(const tdes_schedule &ks, uint32_t out[kDeviceScheduleWords]);
 void round_sequence(const tdes_schedule &ks, int dir, RoundSequence *seq);
-void bitslice_keys(const RoundSequence &seq, BitsliceKeys *out);
+void bitslice_keys(const tdes_schedule &ks, int dir, BitsliceKeys *out);
 void spbox_keys(const RoundSequence &seq, SpboxKeys *out);
 
 // Launchers: enqueue on `stream`; return the HIP launch status.
 hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *out,
                            size_t nbytes, hipStream_t stream);
 size_t batch_workspace_bytes(size_t n_msgs);
+hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream);
 hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                         size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
                         hipStream_t stream);

@@ -22,8 +22,8 @@ STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR
 # Exported symbols, checked against include/*.h by the tests.
 SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
            "tdes_last_error", "tdes_abi_version", "tdes_kernel_key_bytes", "tdes_probe_valu",
-           "tdes_probe_copy", "tdes_schedule_upload", "tdes_batch_workspace_bytes",
-           "tdes_batch_submit")
+           "tdes_probe_copy", "tdes_schedule_upload", "tdes_schedule_expand",
+           "tdes_batch_workspace_bytes", "tdes_batch_submit")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -70,6 +70,8 @@ def lib():
         L.tdes_abi_version.restype = ctypes.c_int
         L.tdes_schedule_upload.argtypes = [sched_p, sz, vp, vp]
         L.tdes_schedule_upload.restype = ctypes.c_int
+        L.tdes_schedule_expand.argtypes = [vp, sz, vp, vp]
+        L.tdes_schedule_expand.restype = ctypes.c_int
         L.tdes_batch_workspace_bytes.argtypes = [sz]
         L.tdes_batch_workspace_bytes.restype = sz
         L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp]
@@ -173,6 +175,12 @@ def key_schedules(keys):
 def schedule_upload(schedules, d_dst, stream=0):
     """tdes_schedule_upload of a ctypes array of Schedule to device address d_dst."""
     _check(lib().tdes_schedule_upload(schedules, len(schedules), ctypes.c_void_p(d_dst),
+                                      ctypes.c_void_p(stream)))
+
+
+def schedule_expand(d_keys24, n, d_schedules, stream=0):
+    """tdes_schedule_expand: n 24-byte bundles (device) -> device schedules."""
+    _check(lib().tdes_schedule_expand(ctypes.c_void_p(d_keys24), n, ctypes.c_void_p(d_schedules),
                                       ctypes.c_void_p(stream)))
 
 

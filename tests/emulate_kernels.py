@@ -42,9 +42,19 @@ def _transpose32(x):
 
 
 def _bs_masks(key_bytes):
-    bits = np.frombuffer(key_bytes, dtype="<u4")
-    n = _int_const(_header("bitslice_keys_gen.h"), "kBsNumMasks")
-    return [M32 if (int(bits[i // 32]) >> (i % 32)) & 1 else 0 for i in range(n)]
+    """Expand the kernel's 100 key-mask words into its LDS layout: index
+    48t + o is bit o % 32 of word 2t + o // 32; 2304 + 32g + j is bit j of
+    word 96 + g."""
+    w = [int(v) for v in np.frombuffer(key_bytes, dtype="<u4")]
+    assert len(w) == 100
+    out = []
+    for t in range(48):
+        for o in range(48):
+            out.append(M32 if (w[2 * t + o // 32] >> (o % 32)) & 1 else 0)
+    for g in range(4):
+        for j in range(32):
+            out.append(M32 if (w[96 + g] >> j) & 1 else 0)
+    return out
 
 
 def _int_const(text, name):

@@ -117,3 +117,20 @@ def test_16k_lognormal_batch(torch_dev):
         o, n = int(lay["offsets"][i]), int(lay["lengths"][i])
         want = oracle.tdes_ecb(lay["keys"][i], data[o:o + n], bool(lay["dirs"][i]))
         assert np.array_equal(got[o:o + n], want), i
+
+
+def test_device_key_expansion_matches_host(torch_dev):
+    """tdes_schedule_expand (key generation on the GPU) writes exactly the
+    bytes tdes_schedule_upload writes from the host key schedule."""
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x304)
+    n = 777
+    keys = W.key_bundles(g, n)
+    keys[5] = np.repeat(keys[5][:8][None], 3, axis=0).reshape(-1)  # K1 = K2 = K3
+    a = torch.zeros(n * T.DEVICE_SCHEDULE_BYTES, dtype=torch.uint8, device="cuda")
+    b = torch.ones_like(a)
+    T.schedule_upload(T.key_schedules(keys), a.data_ptr(), int(torch.cuda.current_stream().cuda_stream))
+    dk = torch.from_numpy(np.ascontiguousarray(keys)).cuda()
+    T.schedule_expand(dk.data_ptr(), n, b.data_ptr(), int(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

@@ -35,6 +35,8 @@ def parse():
                     help="target wall time of the oracle sample (0 disables)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched form (16,384 log-normal messages); 0 disables")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="length of each open-loop serving run (0 disables serving)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of the same size (for PMC scaling)")
     return ap.parse_args()
@@ -114,6 +116,44 @@ def batched_section(steps):
             "per_message_launches_GBps": round(total / t_loop / 1e9, 3),
             "config": "16384 msgs, lognormal median 4 KiB sigma 1, clip 8 B..1 MiB, "
                       "per-message 3-key bundle, 50/50 enc/dec, seed %d" % (W.SEED_BASE + 3)}
+
+
+def serving_section(seconds):
+    """Open-loop Poisson request streams at 5k / 20k / 80k requests/s (sizes
+    70 % 64 B-1 KiB, 25 % 4-64 KiB, 5 % 1-16 MiB, log-uniform within a band;
+    own 3-key bundle each; 50/50 directions; payloads sliced from a 4 GiB
+    device pool), served with continuous batching (4 slots, 32 GiB in-flight
+    budget) and, as the reference, one plain launch per request in arrival
+    order.  Latency runs from each request's scheduled arrival."""
+    import torch
+
+    from paper_2007_10752_amd import serve as S
+    from paper_2007_10752_amd import workloads as W
+    gen = torch.Generator(device="cuda").manual_seed(W.SEED_BASE + 4)
+    pool = torch.randint(0, 256, (4 << 30,), dtype=torch.uint8, device="cuda", generator=gen)
+    arena_bytes = 16 << 30
+    arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device="cuda")
+    base = arena.data_ptr() + (-arena.data_ptr()) % 256
+    res = {"config": "Poisson arrivals, %.1f s per run, sizes 70%% 64 B-1 KiB / 25%% 4-64 KiB "
+                     "/ 5%% 1-16 MiB log-uniform, 3-key bundle and direction per request, "
+                     "budget 32 GiB in flight, 4 slots" % seconds}
+    for rate in (5000, 20000, 80000):
+        trace = W.serving_trace(W.SEED_BASE + 0x500 + rate, rate, seconds)
+        reqs = S.make_requests(trace, pool.data_ptr(), pool.numel(), W.SEED_BASE + 0x600 + rate)
+        for mode, name in ((S.BATCHED, "batched"), (S.PLAIN, "plain")):
+            srv = S.Server(base, arena_bytes, budget_bytes=32 << 30, mode=mode, slots=4,
+                           max_batch_msgs=8192)
+            # warm-up: the first 200 requests of the trace, replayed untimed
+            S.run_open_loop(srv, reqs[:200].copy(), trace["arrival"][:200] - trace["arrival"][0])
+            lat, status, wall, st = S.run_open_loop(srv, reqs, trace["arrival"], timeout_s=120)
+            srv.close()
+            r = S.summarize(lat, trace["size"], wall, st, rate, seconds)
+            r["errors"] = int((status != 0).sum())
+            res["%s_%dk" % (name, rate // 1000)] = r
+            print("serve", name, rate, r["p50_ms"], r["p99_ms"], r["GBps"], file=sys.stderr,
+                  flush=True)
+    del pool, arena
+    return res
 
 
 def traffic_from_profile(kernel, nbytes):
@@ -243,10 +283,13 @@ def main():
                               / costs.HBM_PEAK_BYTES, 4),
         },
     }
+    del x, out
+    torch.cuda.empty_cache()
     if args.batched:
-        del x, out
         line["batched"] = batched_section(args.steps)
         print("batched done", file=sys.stderr, flush=True)
+    if args.serve_seconds > 0:
+        line["served"] = serving_section(args.serve_seconds)
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(key, host, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -38,6 +38,11 @@ tdes_status check_buffers(const void *in, const void *out, size_t nbytes) {
 
 }  // namespace
 
+tdes_status tdes::set_last_error(tdes_status st, const char *msg) {
+    g_last_error = msg;
+    return st;
+}
+
 extern "C" {
 
 tdes_status tdes_key_schedule(const uint8_t key24[24], tdes_schedule *out) {

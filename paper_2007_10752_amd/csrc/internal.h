@@ -35,6 +35,10 @@ struct SpboxKeys {
 constexpr int kDeviceScheduleWords = 200;
 static_assert(kDeviceScheduleWords * 4 == TDES_DEVICE_SCHEDULE_BYTES, "schedule size");
 
+// Record msg as the calling thread's last error (tdes_last_error) and
+// return st.
+tdes_status set_last_error(tdes_status st, const char *msg);
+
 void device_schedule_words(const tdes_schedule &ks, uint32_t out[kDeviceScheduleWords]);
 void round_sequence(const tdes_schedule &ks, int dir, RoundSequence *seq);
 void bitslice_keys(const tdes_schedule &ks, int dir, BitsliceKeys *out);

@@ -23,7 +23,9 @@ STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR
 SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
            "tdes_last_error", "tdes_abi_version", "tdes_kernel_key_bytes", "tdes_probe_valu",
            "tdes_probe_copy", "tdes_schedule_upload", "tdes_schedule_expand",
-           "tdes_batch_workspace_bytes", "tdes_batch_submit")
+           "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
+           "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
+           "tdes_server_release", "tdes_server_get_stats", "tdes_server_now")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32

@@ -136,9 +136,13 @@ def make_requests(trace, pool_ptr, pool_bytes, seed):
 
 def run_open_loop(server, reqs, arrival, on_complete=None, timeout_s=60.0):
     """Replay requests at their scheduled arrival times (seconds from start).
-    Returns per-request latency (scheduled arrival -> completion seen), the
+    Requests are tagged with their position in ``reqs`` (the completions
+    handed to on_complete carry that position as their tag).  Returns
+    per-request latency (scheduled arrival -> completion seen), status, the
     wall time from start to the last completion, and the server's stats."""
     n = len(reqs)
+    reqs = np.array(reqs, dtype=REQUEST, copy=True)
+    reqs["tag"] = np.arange(n, dtype=np.uint64)
     lat = np.full(n, np.nan)
     status = np.zeros(n, dtype=np.int32)
     done = 0

@@ -43,40 +43,57 @@ __device__ __forceinline__ uint64_t slices_of(const tdes_msg &m, size_t n_sched,
     return ok ? (m.nbytes + kSlice - 1) / kSlice : 0;
 }
 
+// Inclusive scan of v over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_scan(uint64_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t u = __shfl_up(v, d, kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// One workgroup walks the descriptors in tiles of 1024 (coalesced loads,
+// the next tile's loads issued before the current tile is scanned), scanning
+// each tile with wave shuffles and carrying the running total.
 __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg *msgs, size_t n,
                                                                  size_t n_sched, uint64_t *ws) {
-    __shared__ uint64_t part[kScanThreads];
-    __shared__ uint32_t nbad[kScanThreads];
-    const size_t per = (n + kScanThreads - 1) / kScanThreads;
-    const size_t lo = min(n, (size_t)threadIdx.x * per), hi = min(n, lo + per);
-    uint64_t sum = 0;
-    uint32_t bad_count = 0;
-    for (size_t i = lo; i < hi; i++) {
-        bool bad;
-        sum += slices_of(msgs[i], n_sched, &bad);
-        bad_count += bad;
-    }
-    part[threadIdx.x] = sum;
-    nbad[threadIdx.x] = bad_count;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive scan
-        const uint64_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
-        const uint32_t b = threadIdx.x >= (unsigned)d ? nbad[threadIdx.x - d] : 0;
+    constexpr int kWaves = kScanThreads / kWave;
+    __shared__ uint64_t wave_tot[kWaves];
+    __shared__ uint32_t wave_bad[kWaves];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    uint64_t run = 0, bad_total = 0;
+    tdes_msg next{};
+    if (threadIdx.x < n) next = msgs[threadIdx.x];
+    for (size_t base = 0; base < n; base += kScanThreads) {
+        const size_t i = base + threadIdx.x;
+        const tdes_msg cur = next;
+        if (i + kScanThreads < n) next = msgs[i + kScanThreads];
+        bool bad = false;
+        const uint64_t v = i < n ? slices_of(cur, n_sched, &bad) : 0;
+        bad = bad && i < n;
+        const uint64_t incl = wave_scan(v, lane);
+        const uint64_t nb = __popcll(__ballot(bad));
+        if (lane == kWave - 1) {
+            wave_tot[w] = incl;
+            wave_bad[w] = (uint32_t)nb;
+        }
         __syncthreads();
-        part[threadIdx.x] += v;
-        nbad[threadIdx.x] += b;
+        uint64_t before = 0, tile = 0, tile_bad = 0;
+        for (int k = 0; k < kWaves; k++) {
+            before += k < w ? wave_tot[k] : 0;
+            tile += wave_tot[k];
+            tile_bad += wave_bad[k];
+        }
+        if (i < n) ws[kWsHeader + i] = run + before + incl - v;
+        run += tile;
+        bad_total += tile_bad;
         __syncthreads();
     }
-    uint64_t run = part[threadIdx.x] - sum;
-    for (size_t i = lo; i < hi; i++) {
-        ws[kWsHeader + i] = run;
-        bool bad;
-        run += slices_of(msgs[i], n_sched, &bad);
-    }
-    if (threadIdx.x == kScanThreads - 1) {
-        ws[0] = part[kScanThreads - 1];
-        ws[1] = nbad[kScanThreads - 1];
-        ws[kWsHeader + n] = part[kScanThreads - 1];
+    if (threadIdx.x == 0) {
+        ws[0] = run;
+        ws[1] = bad_total;
+        ws[kWsHeader + n] = run;
     }
 }
 
@@ -95,9 +112,27 @@ struct LaneRounds {
     __device__ __forceinline__ LaneMasks masks(uint2 w) const { return LaneMasks{w.x, w.y}; }
 };
 
+// Round masks from words the whole wave shares (a wave inside one
+// message): scalar loads, scalar bit extraction, scalar VALU operands.
+struct WaveMasks {
+    uint32_t lo, hi;
+    __device__ __forceinline__ uint32_t operator()(int i) const {
+        const uint32_t w = i < 32 ? lo : hi;
+        return (uint32_t)(((int32_t)(w << (31 - (i < 32 ? i : i - 32)))) >> 31);
+    }
+};
+struct WaveRounds {
+    const uint32_t *kw;  // wave-uniform
+    __device__ __forceinline__ uint2 load(int t) const {
+        return *reinterpret_cast<const uint2 *>(kw + 2 * t);
+    }
+    __device__ __forceinline__ WaveMasks masks(uint2 w) const { return WaveMasks{w.x, w.y}; }
+};
+
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TDES_BATCH_MIN_WAVES, 8)))
-void batch_bitslice_kernel(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sched,
-                           size_t n_sched, const uint8_t *in, uint8_t *out, const uint64_t *ws) {
+void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, size_t n_msgs,
+                           const uint32_t *__restrict__ sched, size_t n_sched, const uint8_t *in,
+                           uint8_t *out, const uint64_t *__restrict__ ws) {
     const uint64_t total = ws[0];
     const uint64_t *first = ws + kWsHeader;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -135,9 +170,21 @@ void batch_bitslice_kernel(const tdes_msg *msgs, size_t n_msgs, const uint32_t *
         }
         transpose32(h0);
         transpose32(h1);
-        des3_planes(
-            h0, h1, LaneRounds{kw},
-            [kw](int g, int i) { return (uint32_t)__builtin_amdgcn_sbfe((int)kw[96 + g], i, 1); });
+        // lane 0's schedule, addressed from the kernel argument so the
+        // compiler may read it with scalar loads
+        const uint32_t s0 = __builtin_amdgcn_readfirstlane(sidx);
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d.dir & 1u);
+        const uint32_t *kw0 = sched + (size_t)s0 * kDeviceScheduleWords + d0 * kDirWords;
+        if (__all(active && sidx == s0 && (d.dir & 1u) == d0)) {
+            // every lane works on the same message and direction
+            des3_planes(h0, h1, WaveRounds{kw0}, [kw0](int g, int i) {
+                return (uint32_t)(((int32_t)(kw0[96 + g] << (31 - i))) >> 31);
+            });
+        } else {
+            des3_planes(h0, h1, LaneRounds{kw}, [kw](int g, int i) {
+                return (uint32_t)__builtin_amdgcn_sbfe((int)kw[96 + g], i, 1);
+            });
+        }
         transpose32(h0);
         transpose32(h1);
 #pragma unroll
@@ -182,6 +229,14 @@ hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, h
     if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
     hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, keys24, n,
                        schedules);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
+                                 size_t n_schedules, const uint8_t *in, uint8_t *out,
+                                 const uint64_t *ws, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(resident_blocks()), dim3(kThreads), 0, stream,
+                       msgs, n_msgs, schedules, n_schedules, in, out, ws);
     return hipGetLastError();
 }
 

@@ -49,6 +49,12 @@ hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *ou
                            size_t nbytes, hipStream_t stream);
 size_t batch_workspace_bytes(size_t n_msgs);
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream);
+// The batched cipher alone, for a workspace whose first-slice table the
+// caller filled already ([0] total slices, [1] 0, [2 + i] first slice of
+// message i, [2 + n] total; a message has ceil(nbytes / 256) slices).
+hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
+                                 size_t n_schedules, const uint8_t *in, uint8_t *out,
+                                 const uint64_t *ws, hipStream_t stream);
 hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                         size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
                         hipStream_t stream);

@@ -72,6 +72,19 @@ struct Active {
     double t_submit, t_admit;
 };
 
+// A slot's staging area, one pinned host buffer mirrored by one device
+// buffer so a batch needs a single copy: [first-slice table as the batched
+// cipher's workspace | descriptors | key bundles].
+struct Staging {
+    size_t ws_off = 0, msgs_off = 0, keys_off = 0, bytes = 0;
+    void layout(size_t n) {
+        ws_off = 0;
+        msgs_off = (tdes::batch_workspace_bytes(n) + 255) / 256 * 256;
+        keys_off = msgs_off + (n * sizeof(tdes_msg) + 255) / 256 * 256;
+        bytes = keys_off + n * 24;
+    }
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -80,10 +93,9 @@ struct Slot {
     double t_launch = 0;
     uint32_t polls_left = 0;
     std::vector<Active> reqs;
-    tdes_msg *h_msgs = nullptr, *d_msgs = nullptr;
-    uint8_t *h_keys = nullptr, *d_keys = nullptr;
+    Staging lay;
+    uint8_t *h_stage = nullptr, *d_stage = nullptr;
     uint32_t *d_sched = nullptr;
-    uint64_t *d_ws = nullptr;
 };
 
 struct PlainEntry {
@@ -181,6 +193,25 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
         sl.polls_left = s->cfg.test_polls > 1 ? s->cfg.test_polls - 1 : 1;
         return TDES_OK;
     }
+    hipError_t e;
+    if (n == 1) {
+        // a batch of one: the plain kernel with host-built key masks (no
+        // copies, one launch) has the lowest latency
+        const Active &a = sl.reqs[0];
+        tdes_schedule ks;
+        for (int b = 0; b < 3; b++) tdes::des_round_keys(a.req.key24 + 8 * b, ks.k[b]);
+        tdes::BitsliceKeys k;
+        tdes::bitslice_keys(ks, (int)a.req.dir, &k);
+        e = tdes::launch_bitslice(k, static_cast<const uint8_t *>(a.req.d_in),
+                                  static_cast<uint8_t *>(s->cfg.d_arena) + a.out_off,
+                                  a.req.nbytes, sl.stream);
+        if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+        return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
+    }
+    uint64_t *ws = reinterpret_cast<uint64_t *>(sl.h_stage + sl.lay.ws_off);
+    tdes_msg *msgs = reinterpret_cast<tdes_msg *>(sl.h_stage + sl.lay.msgs_off);
+    uint8_t *keys = sl.h_stage + sl.lay.keys_off;
+    uint64_t total = 0;
     for (size_t i = 0; i < n; i++) {
         const Active &a = sl.reqs[i];
         tdes_msg m;
@@ -189,17 +220,23 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
         m.nbytes = a.req.nbytes;
         m.sched_idx = (uint32_t)i;
         m.dir = a.req.dir;
-        sl.h_msgs[i] = m;
-        memcpy(sl.h_keys + 24 * i, a.req.key24, 24);
+        msgs[i] = m;
+        memcpy(keys + 24 * i, a.req.key24, 24);
+        ws[2 + i] = total;
+        total += (a.req.nbytes + 255) / 256;  // 256-byte lane slices
     }
-    hipError_t e = hipMemcpyAsync(sl.d_msgs, sl.h_msgs, n * sizeof(tdes_msg),
-                                  hipMemcpyHostToDevice, sl.stream);
+    ws[0] = total;
+    ws[1] = 0;
+    ws[2 + n] = total;
+    const size_t bytes = sl.lay.keys_off + 24 * n;
+    e = hipMemcpyAsync(sl.d_stage, sl.h_stage, bytes, hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.d_keys, sl.h_keys, n * 24, hipMemcpyHostToDevice, sl.stream);
-    if (e == hipSuccess) e = tdes::launch_expand(sl.d_keys, n, sl.d_sched, sl.stream);
+        e = tdes::launch_expand(sl.d_stage + sl.lay.keys_off, n, sl.d_sched, sl.stream);
     if (e == hipSuccess)
-        e = tdes::launch_batch(sl.d_msgs, n, sl.d_sched, n, nullptr,
-                               static_cast<uint8_t *>(s->cfg.d_arena), sl.d_ws, sl.stream);
+        e = tdes::launch_batch_prefixed(
+            reinterpret_cast<const tdes_msg *>(sl.d_stage + sl.lay.msgs_off), n, sl.d_sched, n,
+            nullptr, static_cast<uint8_t *>(s->cfg.d_arena),
+            reinterpret_cast<const uint64_t *>(sl.d_stage + sl.lay.ws_off), sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
 }
@@ -286,12 +323,9 @@ tdes_status progress_plain(tdes_server *s) {
 void free_device(tdes_server *s) {
     for (Slot &sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.h_msgs) (void)hipHostFree(sl.h_msgs);
-        if (sl.h_keys) (void)hipHostFree(sl.h_keys);
-        if (sl.d_msgs) (void)hipFree(sl.d_msgs);
-        if (sl.d_keys) (void)hipFree(sl.d_keys);
+        if (sl.h_stage) (void)hipHostFree(sl.h_stage);
+        if (sl.d_stage) (void)hipFree(sl.d_stage);
         if (sl.d_sched) (void)hipFree(sl.d_sched);
-        if (sl.d_ws) (void)hipFree(sl.d_ws);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
@@ -335,12 +369,10 @@ tdes_status tdes_server_create(const tdes_server_config *cfg, tdes_server **out)
             if (!s->device) continue;
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_msgs, n * sizeof(tdes_msg), 0);
-            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_keys, n * 24, 0);
-            if (e == hipSuccess) e = hipMalloc((void **)&sl.d_msgs, n * sizeof(tdes_msg));
-            if (e == hipSuccess) e = hipMalloc((void **)&sl.d_keys, n * 24);
+            sl.lay.layout(n);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_stage, sl.lay.bytes, 0);
+            if (e == hipSuccess) e = hipMalloc((void **)&sl.d_stage, sl.lay.bytes);
             if (e == hipSuccess) e = hipMalloc((void **)&sl.d_sched, n * TDES_DEVICE_SCHEDULE_BYTES);
-            if (e == hipSuccess) e = hipMalloc((void **)&sl.d_ws, tdes::batch_workspace_bytes(n));
         }
     }
     if (e != hipSuccess) {

@@ -44,30 +44,70 @@ constexpr int kBufferFlags = 0x00020000;
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
-// Round masks read from LDS (uniform address: broadcast to the wave).
-struct LdsMasks {
-    const uint32_t *p;
-    __device__ __forceinline__ uint32_t operator()(int i) const { return p[i]; }
+#ifndef TDES_BS_PIPE
+#define TDES_BS_PIPE 2  // S-boxes between a mask request and its use
+#endif
+
+// Masks of one S-box read from LDS: a uniform address, so the 8 words are
+// broadcast to the wave and enter the VALU as vector operands (full issue
+// rate; a scalar operand halves it).
+struct LdsBoxLoad {
+    // n (0, 2 or 4) is a compile-time constant after inlining; only words that
+    // are used are read, so no read's destination register is reused while
+    // the read is in flight
+    __device__ __forceinline__ void operator()(BsBoxMasks &m, const uint32_t *p, int n) const {
+        // volatile keeps each read where it is issued (otherwise the reads
+        // that cross the loop back edge are folded into reads at first use)
+        typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
+        typedef const volatile __attribute__((address_space(3))) v2u lds_v2u;
+        const v4u a = *(lds_v4u *)p;
+        m.o[0] = a[0]; m.o[1] = a[1]; m.o[2] = a[2]; m.o[3] = a[3];
+        if (n == 4) {
+            const v4u b = *(lds_v4u *)(p + 4);
+            m.e[0] = b[0]; m.e[1] = b[1]; m.e[2] = b[2]; m.e[3] = b[3];
+        } else if (n == 2) {
+            const v2u b = *(lds_v2u *)(p + 4);
+            m.e[0] = b[0]; m.e[1] = b[1];
+        }
+    }
 };
-struct LdsRounds {
+
+// Runs the rounds with each S-box's masks requested TDES_BS_PIPE boxes ahead.
+struct LdsPipedRounds {
     const uint32_t *km;
-    __device__ __forceinline__ const uint32_t *load(int t) const { return km + kBsRoundMasks * t; }
-    __device__ __forceinline__ LdsMasks masks(const uint32_t *p) const { return LdsMasks{p}; }
+    BsBoxMasks pm[8];
+    __device__ __forceinline__ void start() {
+#pragma unroll
+        for (int j = 0; j < TDES_BS_PIPE; j++) LdsBoxLoad{}(pm[j], km + kBsBoxMasks * j, BS_BOX_NDUP[j]);
+    }
+    template <int PH>
+    __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
+        bs_round_piped<TDES_BS_PIPE>(d, r, km + kBsRoundMasks * t, pm, LdsBoxLoad{});
+    }
 };
 
 template <bool VEC16>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
 void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
-    // Expand the launch's key masks (bits) into 0 / ~0 words in LDS.  Read
-    // back with a uniform address they are broadcast to every lane and enter
-    // the VALU as vector operands (full issue rate; a scalar operand halves it).
+    // Expand the launch's key masks (bits) into 0 / ~0 words in LDS.  Past
+    // the 48 rounds the pipeline requests kBsBoxMasks * TDES_BS_PIPE words
+    // that are never used; they fall inside the extra groups.
+    static_assert(kBsNumMasks - kBsInitY >= kBsBoxMasks * TDES_BS_PIPE, "mask pipeline overrun");
     __shared__ __align__(16) uint32_t km[kBsNumMasks];
     for (int i = threadIdx.x; i < kBsNumMasks; i += kWave * kWavesPerBlock) {
-        // LDS index 48t + o <- bit o % 32 of word 2t + o / 32; 2304 + 32g + j <- bit j of word 96 + g
-        const int t = i / kBsRoundMasks, o = i % kBsRoundMasks;
-        const int word = i < kBsInitY ? 2 * t + o / 32 : 96 + (i - kBsInitY) / 32;
-        const int bit = i < kBsInitY ? o % 32 : (i - kBsInitY) % 32;
-        km[i] = 0u - ((keys.w[word] >> bit) & 1u);
+        // round t, box j, slot s < 4: bit 4j + s of word 2t (output XOR masks);
+        // slot s >= 4: bit kBsBoxDup[4j + s - 4] of word 2t + 1 (second uses);
+        // extra group g, entry n: bit n of word 96 + g
+        int word, bit;
+        if (i < kBsInitY) {
+            const int t = i / kBsRoundMasks, j = (i % kBsRoundMasks) / kBsBoxMasks, sl = i % kBsBoxMasks;
+            word = 2 * t + (sl >= 4);
+            bit = sl < 4 ? 4 * j + sl : kBsBoxDup[4 * j + sl - 4];
+        } else {
+            word = 96 + (i - kBsInitY) / 32;
+            bit = (i - kBsInitY) % 32;
+        }
+        km[i] = bit < 0 ? 0u : 0u - ((keys.w[word] >> bit) & 1u);
     }
     __syncthreads();
 
@@ -114,14 +154,13 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     transpose32(h1);
 
     const uint32_t *kml = km;
-    des3_planes(
-        h0, h1, LdsRounds{kml},
-        [kml](int g, int i) {
-            return kml[(g == kGroupInitY     ? kBsInitY
-                        : g == kGroupRemask16 ? kBsRemask16
-                        : g == kGroupRemask32 ? kBsRemask32
-                                              : kBsFinalX) + i];
-        });
+    LdsPipedRounds rr{kml};
+    des3_planes(h0, h1, rr, [kml](int g, int i) {
+        return kml[(g == kGroupInitY     ? kBsInitY
+                    : g == kGroupRemask16 ? kBsRemask16
+                    : g == kGroupRemask32 ? kBsRemask32
+                                          : kBsFinalX) + i];
+    });
     transpose32(h0);
     transpose32(h1);
 

@@ -49,51 +49,61 @@ __device__ __forceinline__ void transpose32(uint32_t (&x)[32]) {
 // rounds 16 and 32, final unmask of X.
 enum { kGroupInitY = 0, kGroupRemask16 = 1, kGroupRemask32 = 2, kGroupFinalX = 3 };
 
+// Round masks fetched a whole round at a time: rm.load(t) fetches what
+// round t needs and rm.masks(v) turns it into the mask source bs_round reads.
+// Fetches are issued two rounds ahead, so memory latency overlaps the two
+// rounds before.
+template <class RoundMasks>
+struct PrefetchRounds {
+    RoundMasks rm;
+    decltype(rm.load(0)) buf[2];
+    __device__ __forceinline__ void start() {
+        buf[0] = rm.load(0);
+        buf[1] = rm.load(1);
+    }
+    // PH = t % 2, known at compile time so buf stays in registers
+    template <int PH>
+    __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
+        const auto next = rm.load(t + 2);  // past round 47: harmless, unused
+        bs_round(d, r, rm.masks(buf[PH]));
+        buf[PH] = next;
+    }
+};
+
 // 3DES-EDE on 32 blocks held as planes h0 (word 0) and h1 (word 1), in
-// place.  Round masks come from `rm`: rm.load(t) fetches what round t needs
-// (issued two rounds ahead, so memory latency overlaps the rounds before)
-// and rm.masks(v) turns it into the mask source bs_round reads.  em(g, i)
-// gives mask i of extra group g.
-template <class RoundMasks, class ExtraMasks>
+// place.  rr runs the rounds: rr.start() once, then rr.round<t % 2>(d, r, t)
+// for t = 0..47 (d ^= f(r, K_t)).  em(g, i) gives mask i of extra group g.
+template <class RoundRunner, class ExtraMasks>
 __device__ __forceinline__ void des3_planes(uint32_t (&h0)[32], uint32_t (&h1)[32],
-                                            const RoundMasks &rm, const ExtraMasks &em) {
+                                            RoundRunner &rr, const ExtraMasks &em) {
     uint32_t X[32], Y[32];
 #pragma unroll
     for (int i = 0; i < 32; i++) {
         X[i] = BS_IP_L[i] < 32 ? h0[BS_IP_L[i]] : h1[BS_IP_L[i] - 32];
         Y[i] = (BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32]) ^ em(kGroupInitY, i);
     }
-    auto a = rm.load(0), b = rm.load(1);
+    rr.start();
     // Pass 1 (L = X, R = Y); ends with X = L16, Y = R16.
 #pragma unroll 1
     for (int r = 0; r < 16; r += 2) {
-        const auto na = rm.load(r + 2), nb = rm.load(r + 3);
-        bs_round(X, Y, rm.masks(a));
-        bs_round(Y, X, rm.masks(b));
-        a = na;
-        b = nb;
+        rr.template round<0>(X, Y, r);
+        rr.template round<1>(Y, X, r + 1);
     }
     // Pass 2 starts from R16 || L16 of pass 1: L = Y, R = X.
 #pragma unroll
     for (int i = 0; i < 32; i++) X[i] ^= em(kGroupRemask16, i);
 #pragma unroll 1
     for (int r = 16; r < 32; r += 2) {
-        const auto na = rm.load(r + 2), nb = rm.load(r + 3);
-        bs_round(Y, X, rm.masks(a));
-        bs_round(X, Y, rm.masks(b));
-        a = na;
-        b = nb;
+        rr.template round<0>(Y, X, r);
+        rr.template round<1>(X, Y, r + 1);
     }
     // Pass 3: L = X, R = Y again; ends with X = L16, Y = R16.
 #pragma unroll
     for (int i = 0; i < 32; i++) Y[i] ^= em(kGroupRemask32, i);
 #pragma unroll 1
     for (int r = 32; r < 48; r += 2) {
-        const auto na = rm.load(r + 2), nb = rm.load(r + 3);  // 48, 49: harmless, unused
-        bs_round(X, Y, rm.masks(a));
-        bs_round(Y, X, rm.masks(b));
-        a = na;
-        b = nb;
+        rr.template round<0>(X, Y, r);
+        rr.template round<1>(Y, X, r + 1);
     }
 #pragma unroll
     for (int i = 0; i < 32; i++) X[i] ^= em(kGroupFinalX, i);

@@ -41,19 +41,27 @@ def _transpose32(x):
     return [sum(((x[b] >> p) & 1) << b for b in range(32)) for p in range(32)]
 
 
-def _bs_masks(key_bytes):
-    """Expand the kernel's 100 key-mask words into its LDS layout: index
-    48t + o is bit o % 32 of word 2t + o // 32; 2304 + 32g + j is bit j of
+def _bs_masks(key_bytes, box_dup, c):
+    """Expand the kernel's 100 key-mask words into its LDS layout: round t,
+    box j, slot s at kBsRoundMasks*t + kBsBoxMasks*j + s is bit 4j + s of
+    word 2t (s < 4) or bit box_dup[4j + s - 4] of word 2t + 1 (s >= 4, 0 if
+    that is -1); extra group g, entry n at kBsInitY + 32g + n is bit n of
     word 96 + g."""
     w = [int(v) for v in np.frombuffer(key_bytes, dtype="<u4")]
     assert len(w) == 100
-    out = []
+    bit = lambda word, b: M32 if (w[word] >> b) & 1 else 0
+    out = [0] * c["kBsNumMasks"]
     for t in range(48):
-        for o in range(48):
-            out.append(M32 if (w[2 * t + o // 32] >> (o % 32)) & 1 else 0)
+        for j in range(8):
+            base = c["kBsRoundMasks"] * t + c["kBsBoxMasks"] * j
+            for q in range(4):
+                out[base + q] = bit(2 * t, 4 * j + q)
+            for i in range(4):
+                k = box_dup[4 * j + i]
+                out[base + 4 + i] = 0 if k < 0 else bit(2 * t + 1, k)
     for g in range(4):
-        for j in range(32):
-            out.append(M32 if (w[96 + g] >> j) & 1 else 0)
+        for n in range(32):
+            out[c["kBsInitY"] + 32 * g + n] = bit(96 + g, n)
     return out
 
 
@@ -71,11 +79,12 @@ def bitslice_ecb(key_bytes, data):
     e_src = _int_array(ktext, "kBsESrc")
     dup_e = _int_array(ktext, "kBsDupE")
     out_word = _int_array(ktext, "kBsOutWord")
-    c = {k: _int_const(ktext, k) for k in ("kBsRoundMasks", "kBsInitY", "kBsRemask16",
-                                           "kBsRemask32", "kBsFinalX")}
-    km = _bs_masks(key_bytes)
+    c = {k: _int_const(ktext, k) for k in ("kBsBoxMasks", "kBsRoundMasks", "kBsInitY",
+                                           "kBsRemask16", "kBsRemask32", "kBsFinalX",
+                                           "kBsNumMasks")}
+    box_dup = _int_array(ktext, "kBsBoxDup")
+    km = _bs_masks(key_bytes, box_dup, c)
     nets = load_networks()
-    dup_of = {e: k for k, e in enumerate(dup_e)}
 
     d = np.asarray(data, dtype=np.uint8)
     nblk = d.size // 8
@@ -88,19 +97,24 @@ def bitslice_ecb(key_bytes, data):
     X = [plane[i] for i in ip_l]
     Y = [plane[i] ^ km[c["kBsInitY"] + n] for n, i in enumerate(ip_r)]
 
+    dup_set = set(dup_e)
+
     def rnd(dst, src, t):
-        m = km[c["kBsRoundMasks"] * t:]
         for box in range(8):
-            sig = []
+            m = km[c["kBsRoundMasks"] * t + c["kBsBoxMasks"] * box:]
+            sig, i = [], 0
             for q in range(6):
                 e = 6 * box + q
                 v = src[e_src[e]]
-                sig.append(v ^ m[32 + dup_of[e]] if e in dup_of else v)
+                if e in dup_set:        # i-th second-use input of this box
+                    v ^= m[4 + i]
+                    i += 1
+                sig.append(v)
             for a, b, cc, imm in nets[box]["gates"]:
                 sig.append(_lut3(imm, sig[a], sig[b], sig[cc]))
             for q, (sg, neg) in enumerate(nets[box]["outs"]):
                 j = out_word[4 * box + q]
-                dst[j] ^= sig[sg] ^ (M32 if neg else 0) ^ m[4 * box + q]
+                dst[j] ^= sig[sg] ^ (M32 if neg else 0) ^ m[q]
 
     for t in range(0, 16, 2):
         rnd(X, Y, t)

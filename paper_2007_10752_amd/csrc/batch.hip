@@ -177,15 +177,15 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, size_t n_msgs,
         const uint32_t *kw0 = sched + (size_t)s0 * kDeviceScheduleWords + d0 * kDirWords;
         if (__all(active && sidx == s0 && (d.dir & 1u) == d0)) {
             // every lane works on the same message and direction
-            PrefetchRounds<WaveRounds> rr{WaveRounds{kw0}};
-            des3_planes(h0, h1, rr, [kw0](int g, int i) {
+            auto rr = prefetch_rounds(WaveRounds{kw0}, [kw0](int g, int i) {
                 return (uint32_t)(((int32_t)(kw0[96 + g] << (31 - i))) >> 31);
             });
+            des3_planes(h0, h1, rr);
         } else {
-            PrefetchRounds<LaneRounds> rr{LaneRounds{kw}};
-            des3_planes(h0, h1, rr, [kw](int g, int i) {
+            auto rr = prefetch_rounds(LaneRounds{kw}, [kw](int g, int i) {
                 return (uint32_t)__builtin_amdgcn_sbfe((int)kw[96 + g], i, 1);
             });
+            des3_planes(h0, h1, rr);
         }
         transpose32(h0);
         transpose32(h1);

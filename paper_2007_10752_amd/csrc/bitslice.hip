@@ -29,7 +29,7 @@
 #include "internal.h"
 
 #ifndef TDES_BS_MIN_WAVES
-#define TDES_BS_MIN_WAVES 3  // waves per SIMD the register budget must allow
+#define TDES_BS_MIN_WAVES 4  // waves per SIMD the register budget must allow
 #endif
 
 namespace tdes {
@@ -84,51 +84,61 @@ struct LdsPipedRounds {
     __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
         bs_round_piped<TDES_BS_PIPE>(d, r, km + kBsRoundMasks * t, pm, LdsBoxLoad{});
     }
+    // XOR extra group g into a, 4 masks at a time with the next 4 already
+    // requested (32 masks in flight at once would need 32 more registers)
+    __device__ __forceinline__ void extra(int g, uint32_t (&a)[32]) const {
+        typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
+        const uint32_t *p = km + (g == kGroupInitY     ? kBsInitY
+                                  : g == kGroupRemask16 ? kBsRemask16
+                                  : g == kGroupRemask32 ? kBsRemask32
+                                                        : kBsFinalX);
+        v4u m[2];
+        m[0] = *(lds_v4u *)p;
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            if (b < 7) m[(b + 1) & 1] = *(lds_v4u *)(p + 4 * b + 4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; i++) a[4 * b + i] ^= m[b & 1][i];
+        }
+    }
 };
+
+// kBsBoxDup[4j + i] for a j known only at run time, without a memory
+// lookup: column i packed into 5-bit fields of one constant (31: unused).
+constexpr uint64_t dup_column(int i) {
+    uint64_t c = 0;
+    for (int j = 0; j < 8; j++) c |= (uint64_t)(kBsBoxDup[4 * j + i] & 31) << (5 * j);
+    return c;
+}
+__device__ __forceinline__ int box_dup(int j, int i) {
+    constexpr uint64_t kCol[4] = {dup_column(0), dup_column(1), dup_column(2), dup_column(3)};
+    const int k = (int)((kCol[i] >> (5 * j)) & 31u);
+    return k == 31 ? -1 : k;
+}
 
 template <bool VEC16>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
 void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
-    // Expand the launch's key masks (bits) into 0 / ~0 words in LDS.  Past
-    // the 48 rounds the pipeline requests kBsBoxMasks * TDES_BS_PIPE words
-    // that are never used; they fall inside the extra groups.
-    static_assert(kBsNumMasks - kBsInitY >= kBsBoxMasks * TDES_BS_PIPE, "mask pipeline overrun");
-    __shared__ __align__(16) uint32_t km[kBsNumMasks];
-    for (int i = threadIdx.x; i < kBsNumMasks; i += kWave * kWavesPerBlock) {
-        // round t, box j, slot s < 4: bit 4j + s of word 2t (output XOR masks);
-        // slot s >= 4: bit kBsBoxDup[4j + s - 4] of word 2t + 1 (second uses);
-        // extra group g, entry n: bit n of word 96 + g
-        int word, bit;
-        if (i < kBsInitY) {
-            const int t = i / kBsRoundMasks, j = (i % kBsRoundMasks) / kBsBoxMasks, sl = i % kBsBoxMasks;
-            word = 2 * t + (sl >= 4);
-            bit = sl < 4 ? 4 * j + sl : kBsBoxDup[4 * j + sl - 4];
-        } else {
-            word = 96 + (i - kBsInitY) / 32;
-            bit = (i - kBsInitY) % 32;
-        }
-        km[i] = bit < 0 ? 0u : 0u - ((keys.w[word] >> bit) & 1u);
-    }
-    __syncthreads();
-
     // the wave index is uniform within the wave; say so, so the chunk base
     // and the buffer resources below live in scalar registers
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const size_t chunk = (size_t)blockIdx.x * kWavesPerBlock + wave;
     const size_t base = chunk * kChunk;
-    if (base >= nbytes) return;  // wave-uniform
+    const bool live = base < nbytes;  // wave-uniform
     const uint32_t lane_off = (threadIdx.x % kWave) * 16u;
     // Bytes of this chunk that exist: 16384 except in the last chunk.  The
     // chunk is addressed through buffer resources sized to it, so the
     // hardware range check zero-fills loads and drops stores past the end;
     // the partial path uses 8-byte accesses, each wholly in or out of range.
-    const uint32_t avail = (uint32_t)(nbytes - base < kChunk ? nbytes - base : kChunk);
+    const uint32_t avail = live ? (uint32_t)(nbytes - base < kChunk ? nbytes - base : kChunk) : 0u;
     const bool whole = VEC16 && avail == (uint32_t)kChunk;
     const __amdgpu_buffer_rsrc_t src =
         __builtin_amdgcn_make_buffer_rsrc((void *)(in + base), 0, (int)avail, kBufferFlags);
     const __amdgpu_buffer_rsrc_t dst =
         __builtin_amdgcn_make_buffer_rsrc((void *)(out + base), 0, (int)avail, kBufferFlags);
 
+    // Request the chunk: its memory latency overlaps the mask expansion.
     uint32_t h0[32], h1[32];
     if (whole) {
 #pragma unroll
@@ -139,7 +149,7 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
             h0[2 * k + 1] = v[2];
             h1[2 * k + 1] = v[3];
         }
-    } else {
+    } else if (live) {
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const v2u a = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off, k * 1024, 0);
@@ -150,18 +160,52 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
             h1[2 * k + 1] = b[1];
         }
     }
+
+    // Expand the launch's key masks (bits) into 0 / ~0 words in LDS.  A
+    // round's 64 words are one per lane: lane l is slot l % 8 of S-box l / 8,
+    // slot q < 4 bit 4j + q of word 2t (output XOR masks), slot 4 + i bit
+    // kBsBoxDup[4j + i] of word 2t + 1 (second uses).  Wave w builds rounds
+    // w, w + 4, ...; its key words are uniform, read with scalar loads.  Past
+    // the 48 rounds the pipeline requests kBsBoxMasks * TDES_BS_PIPE words
+    // that are never used; they fall inside the extra groups.
+    static_assert(kBsBoxMasks == 8 && kBsRoundMasks == kWave && kWavesPerBlock == 4, "mask layout");
+    static_assert(kBsNumMasks - kBsInitY >= kBsBoxMasks * TDES_BS_PIPE, "mask pipeline overrun");
+    __shared__ __align__(16) uint32_t km[kBsNumMasks];
+    {
+        const int lane = threadIdx.x % kWave, j = lane >> 3, sl = lane & 7;
+        const int d0 = box_dup(j, 0), d1 = box_dup(j, 1), d2 = box_dup(j, 2), d3 = box_dup(j, 3);
+        const int dk = sl == 4 ? d0 : sl == 5 ? d1 : sl == 6 ? d2 : d3;
+        const int bit = sl < 4 ? 4 * j + sl : dk;  // -1: unused slot, mask 0
+        const uint32_t keep = bit < 0 ? 0u : ~0u;
+        const uint32_t sh = bit < 0 ? 0u : (uint32_t)bit;
+#pragma unroll
+        for (int r = 0; r < 48 / kWavesPerBlock; r++) {
+            const int t = (int)wave + kWavesPerBlock * r;
+            // both words as scalars (read once per wave), then a per-lane pick
+            const uint32_t lo = __builtin_amdgcn_readfirstlane(keys.w[2 * t]);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane(keys.w[2 * t + 1]);
+            const uint32_t w = sl < 4 ? lo : hi;
+            km[kBsRoundMasks * t + lane] = (0u - ((w >> sh) & 1u)) & keep;
+        }
+        // extra group g = w, entry n = lane < 32: bit n of word 96 + g
+        if (lane < 32) km[kBsInitY + 32 * wave + lane] = 0u - ((keys.w[96 + wave] >> lane) & 1u);
+    }
+    __syncthreads();
+    if (!live) return;
+
+    // one transpose at a time: interleaved, they hold more words live than
+    // the register budget allows
     transpose32(h0);
+    __builtin_amdgcn_sched_barrier(0);
     transpose32(h1);
+    __builtin_amdgcn_sched_barrier(0);
 
     const uint32_t *kml = km;
     LdsPipedRounds rr{kml};
-    des3_planes(h0, h1, rr, [kml](int g, int i) {
-        return kml[(g == kGroupInitY     ? kBsInitY
-                    : g == kGroupRemask16 ? kBsRemask16
-                    : g == kGroupRemask32 ? kBsRemask32
-                                          : kBsFinalX) + i];
-    });
+    des3_planes(h0, h1, rr);
+    __builtin_amdgcn_sched_barrier(0);
     transpose32(h0);
+    __builtin_amdgcn_sched_barrier(0);
     transpose32(h1);
 
     if (whole) {

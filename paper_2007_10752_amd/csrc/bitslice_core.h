@@ -14,24 +14,39 @@
 
 namespace tdes {
 
+// A constant held in a vector register.  A VALU instruction that reads a
+// scalar register is never issued together with another wave's VALU
+// instruction, so constants the transposes read on every instruction are
+// kept in VGPRs (the asm hides the value, so it is not folded back).
+__device__ __forceinline__ uint32_t vconst(uint32_t c) {
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(c));
+    return v;
+}
+
 // One swap-move stage of the 32x32 transpose: rows i and i+J (i & J == 0)
 // exchange the J-bit groups where row bit J differs from column bit J.
+// Pairs are kept in groups of four by scheduling barriers: the scheduler
+// would otherwise compute a whole stage's new words before retiring the old
+// ones, holding up to 32 more words live.
 template <int J>
 __device__ __forceinline__ void swap_stage(uint32_t (&x)[32]) {
+    constexpr uint32_t c0 = J == 16 ? 0x05040100u : J == 8 ? 0x06020400u
+                          : J == 4  ? 0x0F0F0F0Fu : J == 2 ? 0x33333333u : 0x55555555u;
+    constexpr uint32_t c1 = J == 16 ? 0x07060302u : 0x07030501u;
+    const uint32_t k0 = vconst(c0), k1 = J >= 8 ? vconst(c1) : 0u;
 #pragma unroll
-    for (int i = 0; i < 32; i++) {
+    for (int i = 0, n = 0; i < 32; i++) {
         if (i & J) continue;
+        if (n++ % 4 == 0) __builtin_amdgcn_sched_barrier(0);
         const uint32_t a = x[i], b = x[i + J];
-        if (J == 16) {
-            x[i] = __builtin_amdgcn_perm(b, a, 0x05040100u);
-            x[i + J] = __builtin_amdgcn_perm(b, a, 0x07060302u);
-        } else if (J == 8) {
-            x[i] = __builtin_amdgcn_perm(b, a, 0x06020400u);
-            x[i + J] = __builtin_amdgcn_perm(b, a, 0x07030501u);
+        if (J >= 8) {
+            x[i] = __builtin_amdgcn_perm(b, a, k0);
+            x[i + J] = __builtin_amdgcn_perm(b, a, k1);
         } else {
-            constexpr uint32_t m = J == 4 ? 0x0F0F0F0Fu : J == 2 ? 0x33333333u : 0x55555555u;
-            x[i] = (a & m) | ((b << J) & ~m);
-            x[i + J] = ((a >> J) & m) | (b & ~m);
+            // bit-field inserts under the mask k0
+            x[i] = (a & k0) | ((b << J) & ~k0);
+            x[i + J] = ((a >> J) & k0) | (b & ~k0);
         }
     }
 }
@@ -52,10 +67,11 @@ enum { kGroupInitY = 0, kGroupRemask16 = 1, kGroupRemask32 = 2, kGroupFinalX = 3
 // Round masks fetched a whole round at a time: rm.load(t) fetches what
 // round t needs and rm.masks(v) turns it into the mask source bs_round reads.
 // Fetches are issued two rounds ahead, so memory latency overlaps the two
-// rounds before.
-template <class RoundMasks>
+// rounds before.  em(g, i) gives mask i of extra group g.
+template <class RoundMasks, class ExtraMasks>
 struct PrefetchRounds {
     RoundMasks rm;
+    ExtraMasks em;
     decltype(rm.load(0)) buf[2];
     __device__ __forceinline__ void start() {
         buf[0] = rm.load(0);
@@ -68,20 +84,32 @@ struct PrefetchRounds {
         bs_round(d, r, rm.masks(buf[PH]));
         buf[PH] = next;
     }
+    __device__ __forceinline__ void extra(int g, uint32_t (&a)[32]) const {
+#pragma unroll
+        for (int i = 0; i < 32; i++) a[i] ^= em(g, i);
+    }
 };
+
+template <class RoundMasks, class ExtraMasks>
+__device__ __forceinline__ PrefetchRounds<RoundMasks, ExtraMasks> prefetch_rounds(
+    const RoundMasks &rm, const ExtraMasks &em) {
+    return PrefetchRounds<RoundMasks, ExtraMasks>{rm, em, {}};
+}
 
 // 3DES-EDE on 32 blocks held as planes h0 (word 0) and h1 (word 1), in
 // place.  rr runs the rounds: rr.start() once, then rr.round<t % 2>(d, r, t)
-// for t = 0..47 (d ^= f(r, K_t)).  em(g, i) gives mask i of extra group g.
-template <class RoundRunner, class ExtraMasks>
+// for t = 0..47 (d ^= f(r, K_t)); rr.extra(g, a) XORs extra mask group g
+// into the 32 words a.
+template <class RoundRunner>
 __device__ __forceinline__ void des3_planes(uint32_t (&h0)[32], uint32_t (&h1)[32],
-                                            RoundRunner &rr, const ExtraMasks &em) {
+                                            RoundRunner &rr) {
     uint32_t X[32], Y[32];
 #pragma unroll
     for (int i = 0; i < 32; i++) {
         X[i] = BS_IP_L[i] < 32 ? h0[BS_IP_L[i]] : h1[BS_IP_L[i] - 32];
-        Y[i] = (BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32]) ^ em(kGroupInitY, i);
+        Y[i] = BS_IP_R[i] < 32 ? h0[BS_IP_R[i]] : h1[BS_IP_R[i] - 32];
     }
+    rr.extra(kGroupInitY, Y);
     rr.start();
     // Pass 1 (L = X, R = Y); ends with X = L16, Y = R16.
 #pragma unroll 1
@@ -90,23 +118,20 @@ __device__ __forceinline__ void des3_planes(uint32_t (&h0)[32], uint32_t (&h1)[3
         rr.template round<1>(Y, X, r + 1);
     }
     // Pass 2 starts from R16 || L16 of pass 1: L = Y, R = X.
-#pragma unroll
-    for (int i = 0; i < 32; i++) X[i] ^= em(kGroupRemask16, i);
+    rr.extra(kGroupRemask16, X);
 #pragma unroll 1
     for (int r = 16; r < 32; r += 2) {
         rr.template round<0>(Y, X, r);
         rr.template round<1>(X, Y, r + 1);
     }
     // Pass 3: L = X, R = Y again; ends with X = L16, Y = R16.
-#pragma unroll
-    for (int i = 0; i < 32; i++) Y[i] ^= em(kGroupRemask32, i);
+    rr.extra(kGroupRemask32, Y);
 #pragma unroll 1
     for (int r = 32; r < 48; r += 2) {
         rr.template round<0>(X, Y, r);
         rr.template round<1>(Y, X, r + 1);
     }
-#pragma unroll
-    for (int i = 0; i < 32; i++) X[i] ^= em(kGroupFinalX, i);
+    rr.extra(kGroupFinalX, X);
     // preoutput R16 || L16 = Y || X, then FP as renaming
 #pragma unroll
     for (int q = 0; q < 32; q++) {

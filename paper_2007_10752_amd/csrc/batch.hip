@@ -140,16 +140,36 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, size_t n_msgs,
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t base = ((uint64_t)blockIdx.x * kWavesPerBlock + wave) * kWave; base < total;
          base += stride) {
-        // message holding slice `base`: largest m with first[m] <= base
-        size_t lo = 0, hi = n_msgs;
+        // Message holding slice `base`: the largest m with first[m] <= base
+        // (first[] is non-decreasing, first[n_msgs] = total > base).  A
+        // 64-way search: each step every lane tests one evenly spaced entry
+        // and a ballot keeps the sub-range, so 16k messages take 3 steps.
+        size_t lo = 0, hi = n_msgs;  // first[lo] <= base < first[hi]
         while (hi - lo > 1) {
-            const size_t mid = (lo + hi) / 2;
-            if (first[mid] <= base) lo = mid;
-            else hi = mid;
+            const size_t step = (hi - lo + kWave - 1) / kWave;
+            const size_t idx = lo + (size_t)(lane + 1) * step;
+            const bool le = idx < hi && first[idx] <= base;
+            const size_t k = (size_t)__popcll(__ballot(le));  // tests passed: a prefix of lanes
+            const size_t nlo = lo + k * step, nhi = lo + (k + 1) * step;
+            lo = nlo;
+            hi = nhi < hi ? nhi : hi;
         }
+        // Each lane's message: m0 plus the number of the next 64 message
+        // starts at or before its slice, found by a binary search over the
+        // starts held one per lane.  Past 63 of them (only with empty
+        // messages) the lane walks on.
         const uint64_t s = base + lane;
         const bool active = s < total;
-        size_t m = lo;
+        const size_t nxt = lo + 1 + lane;
+        const uint64_t start_l = nxt <= n_msgs ? first[nxt] : ~0ull;
+        int r = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint64_t b = __shfl(start_l, r + step - 1);
+            if (b <= s) r += step;
+        }
+        // (a lane past the end keeps m0: its count may include first[n_msgs])
+        size_t m = active ? lo + (size_t)r : lo;
         if (active)
             while (first[m + 1] <= s) m++;
         const tdes_msg d = msgs[m];

@@ -54,6 +54,27 @@ def test_small_mixed_batch(torch_dev):
         assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
 
 
+def test_runs_of_empty_and_one_slice_messages(torch_dev):
+    # More than 64 empty messages in a row between non-empty ones, and
+    # stretches where every lane of a wave holds its own message: the cases
+    # the per-lane message lookup handles by walking on past the 64 starts
+    # it searches, and by the search itself.
+    g = W.rng(W.SEED_BASE + 0x304)
+    lengths = np.concatenate([
+        [0] * 70, [256], [0] * 130, (g.integers(1, 33, size=200) * 8),
+        [0] * 65, [8], [0] * 64, [4096], [0] * 3]).astype(np.int64)
+    n = len(lengths)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    data = W.uniform_bytes(g, int(lengths.sum()))
+    _say("batch empty runs", n, int(lengths.sum()))
+    offs, got, b = _run_batch(torch_dev, keys, lengths, dirs, data)
+    assert b.skipped() == 0
+    for i in range(n):
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
 def test_in_place_and_gaps(torch_dev):
     g = W.rng(W.SEED_BASE + 0x301)
     n = 20

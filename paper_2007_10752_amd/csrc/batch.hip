@@ -4,11 +4,11 @@
 // Work unit: a lane slice of 256 bytes (32 blocks) of one message; a
 // message of n bytes has ceil(n / 256) slices.  A single-workgroup scan
 // turns the descriptors into first-slice offsets (in the caller's
-// workspace); then a persistent grid sized to the resident waves walks the
+// workspace); then a grid of twice the resident waves strides over the
 // slices, one per lane, 64 consecutive slices per wave per step.  Each lane
-// finds its message (the wave binary-searches the message of its first
-// slice with scalar loads, each lane walks forward from it), loads its 256
-// bytes, and runs the same bitsliced core as the plain kernel, with its
+// finds its message (a 64-way search for the message of the wave's first
+// slice, then a shuffle search over the next 64 message starts), loads its
+// 256 bytes, and runs the same bitsliced core as the plain kernel, with its
 // message's key masks: two mask words per round read from the device
 // schedule table (cached; identical across lanes of one message) and
 // expanded bit by bit with v_bfe_i32.
@@ -20,6 +20,9 @@
 
 #ifndef TDES_BATCH_MIN_WAVES
 #define TDES_BATCH_MIN_WAVES 3
+#endif
+#ifndef TDES_BATCH_GRID_MULT
+#define TDES_BATCH_GRID_MULT 2  // launched waves per resident wave slot
 #endif
 
 namespace tdes {
@@ -37,8 +40,9 @@ constexpr int kScanThreads = 1024;
 constexpr int kWsHeader = 2;
 
 __device__ __forceinline__ uint64_t slices_of(const tdes_msg &m, size_t n_sched, bool *bad) {
-    const bool ok = (m.nbytes % 8 == 0) && (m.in_off % 8 == 0) && (m.out_off % 8 == 0) &&
-                    (m.sched_idx < n_sched) && (m.dir <= 1);
+    // bitwise, not short-circuit, so that no field is read under a branch
+    const bool ok = (((m.nbytes | m.in_off | m.out_off) % 8) == 0) & (m.sched_idx < n_sched) &
+                    (m.dir <= 1);
     *bad = !ok;
     return ok ? (m.nbytes + kSlice - 1) / kSlice : 0;
 }
@@ -53,30 +57,46 @@ __device__ __forceinline__ uint64_t wave_scan(uint64_t v, int lane) {
     return v;
 }
 
-// One workgroup walks the descriptors in tiles of 1024 (coalesced loads,
-// the next tile's loads issued before the current tile is scanned), scanning
-// each tile with wave shuffles and carrying the running total.
+// One workgroup scans the descriptors in chunks of 16 x 512: wave w owns
+// descriptors w*512 .. w*512 + 511 of the chunk and walks them 64 at a time
+// (coalesced loads, issued together: the index is clamped and the result
+// masked so no load sits under a branch), scanning each step with shuffles
+// and carrying its own running total; one barrier then gives every wave the
+// totals of the waves before it, and the first slices are written
+// (coalesced).  Larger batches loop over chunks, carrying the running total.
+constexpr int kScanSteps = 8;  // 64-descriptor steps per wave and chunk
+
 __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg *msgs, size_t n,
                                                                  size_t n_sched, uint64_t *ws) {
     constexpr int kWaves = kScanThreads / kWave;
+    constexpr size_t kWaveMsgs = (size_t)kWave * kScanSteps;
+    constexpr size_t kChunkMsgs = kWaveMsgs * kWaves;
     __shared__ uint64_t wave_tot[kWaves];
     __shared__ uint32_t wave_bad[kWaves];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     uint64_t run = 0, bad_total = 0;
-    tdes_msg next{};
-    if (threadIdx.x < n) next = msgs[threadIdx.x];
-    for (size_t base = 0; base < n; base += kScanThreads) {
-        const size_t i = base + threadIdx.x;
-        const tdes_msg cur = next;
-        if (i + kScanThreads < n) next = msgs[i + kScanThreads];
-        bool bad = false;
-        const uint64_t v = i < n ? slices_of(cur, n_sched, &bad) : 0;
-        bad = bad && i < n;
-        const uint64_t incl = wave_scan(v, lane);
-        const uint64_t nb = __popcll(__ballot(bad));
-        if (lane == kWave - 1) {
-            wave_tot[w] = incl;
-            wave_bad[w] = (uint32_t)nb;
+    for (size_t base = 0; base < n; base += kChunkMsgs) {
+        const size_t wbase = base + (size_t)w * kWaveMsgs;
+        uint64_t pre[kScanSteps];  // exclusive prefix within the wave's range
+        uint64_t carry = 0;
+        uint32_t nbad = 0;
+#pragma unroll
+        for (int k = 0; k < kScanSteps; k++) {
+            const size_t i = wbase + (size_t)k * kWave + lane;
+            const tdes_msg m = msgs[i < n ? i : n - 1];
+            bool bad = false;
+            const uint64_t vi = slices_of(m, n_sched, &bad);
+            const uint64_t v = i < n ? vi : 0;
+            nbad += (bad && i < n) ? 1u : 0u;
+            const uint64_t incl = wave_scan(v, lane);
+            pre[k] = carry + incl - v;
+            carry += __shfl(incl, kWave - 1, kWave);
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) nbad += __shfl_xor(nbad, d, kWave);
+        if (lane == 0) {
+            wave_tot[w] = carry;
+            wave_bad[w] = nbad;
         }
         __syncthreads();
         uint64_t before = 0, tile = 0, tile_bad = 0;
@@ -85,7 +105,11 @@ __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg
             tile += wave_tot[k];
             tile_bad += wave_bad[k];
         }
-        if (i < n) ws[kWsHeader + i] = run + before + incl - v;
+#pragma unroll
+        for (int k = 0; k < kScanSteps; k++) {
+            const size_t i = wbase + (size_t)k * kWave + lane;
+            if (i < n) ws[kWsHeader + i] = run + before + pre[k];
+        }
         run += tile;
         bad_total += tile_bad;
         __syncthreads();
@@ -231,7 +255,13 @@ __global__ __launch_bounds__(256) void expand_kernel(const uint8_t *keys24, size
     bitslice_mask_words(k, dir, schedules + b * kDeviceScheduleWords + dir * kDirWords);
 }
 
-int resident_blocks() {
+// The batched kernel's grid: TDES_BATCH_GRID_MULT times the workgroups that
+// fit at once.  Each wave strides over the 64-slice groups, so any grid is
+// correct; launching more waves than fit lets the hardware start a new wave
+// wherever one finishes, so the last groups of a batch are spread over the
+// whole GPU instead of being left to the persistent waves' final pass (a
+// wave with no group left exits at once).
+int batch_grid_blocks() {
     static int n = 0;
     if (n == 0) {
         int dev = 0, cus = 0;
@@ -239,7 +269,7 @@ int resident_blocks() {
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
-        n = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock;  // 4 SIMDs per CU
+        n = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock * TDES_BATCH_GRID_MULT;  // 4 SIMDs/CU
     }
     return n;
 }
@@ -257,7 +287,7 @@ hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, h
 hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                                  size_t n_schedules, const uint8_t *in, uint8_t *out,
                                  const uint64_t *ws, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(resident_blocks()), dim3(kThreads), 0, stream,
+    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
                        msgs, n_msgs, schedules, n_schedules, in, out, ws);
     return hipGetLastError();
 }
@@ -271,7 +301,7 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                        n_schedules, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(resident_blocks()), dim3(kThreads), 0, stream,
+    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
                        msgs, n_msgs, schedules, n_schedules, in, out, ws);
     return hipGetLastError();
 }

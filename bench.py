@@ -179,7 +179,8 @@ def kernel_source_hash(kernel):
     counter readings still describe it)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2007_10752_amd", "csrc")
-    files = {"bitslice": ["bitslice.hip", "bitslice_core.h", "generated/bitslice_gen.h"],
+    files = {"bitslice": ["bitslice.hip", "bitslice_core.h", "lds_masks.h",
+                          "generated/bitslice_gen.h"],
              "spbox": ["spbox.hip", "generated/spbox_gen.h"]}[kernel]
     h = hashlib.sha256()
     for name in files:

@@ -25,6 +25,7 @@
 #include <stdint.h>
 
 #include "bitslice_core.h"
+#include "lds_masks.h"
 #include "generated/bitslice_keys_gen.h"
 #include "internal.h"
 
@@ -41,81 +42,6 @@ constexpr int kWavesPerBlock = 4;
 constexpr size_t kChunk = 16384;  // bytes per wave
 // Buffer-resource word 3 for gfx9-family raw (unstructured) buffers.
 constexpr int kBufferFlags = 0x00020000;
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-
-#ifndef TDES_BS_PIPE
-#define TDES_BS_PIPE 2  // S-boxes between a mask request and its use
-#endif
-
-// Masks of one S-box read from LDS: a uniform address, so the 8 words are
-// broadcast to the wave and enter the VALU as vector operands (full issue
-// rate; a scalar operand halves it).
-struct LdsBoxLoad {
-    // n (0, 2 or 4) is a compile-time constant after inlining; only words that
-    // are used are read, so no read's destination register is reused while
-    // the read is in flight
-    __device__ __forceinline__ void operator()(BsBoxMasks &m, const uint32_t *p, int n) const {
-        // volatile keeps each read where it is issued (otherwise the reads
-        // that cross the loop back edge are folded into reads at first use)
-        typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
-        typedef const volatile __attribute__((address_space(3))) v2u lds_v2u;
-        const v4u a = *(lds_v4u *)p;
-        m.o[0] = a[0]; m.o[1] = a[1]; m.o[2] = a[2]; m.o[3] = a[3];
-        if (n == 4) {
-            const v4u b = *(lds_v4u *)(p + 4);
-            m.e[0] = b[0]; m.e[1] = b[1]; m.e[2] = b[2]; m.e[3] = b[3];
-        } else if (n == 2) {
-            const v2u b = *(lds_v2u *)(p + 4);
-            m.e[0] = b[0]; m.e[1] = b[1];
-        }
-    }
-};
-
-// Runs the rounds with each S-box's masks requested TDES_BS_PIPE boxes ahead.
-struct LdsPipedRounds {
-    const uint32_t *km;
-    BsBoxMasks pm[8];
-    __device__ __forceinline__ void start() {
-#pragma unroll
-        for (int j = 0; j < TDES_BS_PIPE; j++) LdsBoxLoad{}(pm[j], km + kBsBoxMasks * j, BS_BOX_NDUP[j]);
-    }
-    template <int PH>
-    __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
-        bs_round_piped<TDES_BS_PIPE>(d, r, km + kBsRoundMasks * t, pm, LdsBoxLoad{});
-    }
-    // XOR extra group g into a, 4 masks at a time with the next 4 already
-    // requested (32 masks in flight at once would need 32 more registers)
-    __device__ __forceinline__ void extra(int g, uint32_t (&a)[32]) const {
-        typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
-        const uint32_t *p = km + (g == kGroupInitY     ? kBsInitY
-                                  : g == kGroupRemask16 ? kBsRemask16
-                                  : g == kGroupRemask32 ? kBsRemask32
-                                                        : kBsFinalX);
-        v4u m[2];
-        m[0] = *(lds_v4u *)p;
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            if (b < 7) m[(b + 1) & 1] = *(lds_v4u *)(p + 4 * b + 4);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < 4; i++) a[4 * b + i] ^= m[b & 1][i];
-        }
-    }
-};
-
-// kBsBoxDup[4j + i] for a j known only at run time, without a memory
-// lookup: column i packed into 5-bit fields of one constant (31: unused).
-constexpr uint64_t dup_column(int i) {
-    uint64_t c = 0;
-    for (int j = 0; j < 8; j++) c |= (uint64_t)(kBsBoxDup[4 * j + i] & 31) << (5 * j);
-    return c;
-}
-__device__ __forceinline__ int box_dup(int j, int i) {
-    constexpr uint64_t kCol[4] = {dup_column(0), dup_column(1), dup_column(2), dup_column(3)};
-    const int k = (int)((kCol[i] >> (5 * j)) & 31u);
-    return k == 31 ? -1 : k;
-}
 
 template <bool VEC16>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
@@ -172,20 +98,14 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     static_assert(kBsNumMasks - kBsInitY >= kBsBoxMasks * TDES_BS_PIPE, "mask pipeline overrun");
     __shared__ __align__(16) uint32_t km[kBsNumMasks];
     {
-        const int lane = threadIdx.x % kWave, j = lane >> 3, sl = lane & 7;
-        const int d0 = box_dup(j, 0), d1 = box_dup(j, 1), d2 = box_dup(j, 2), d3 = box_dup(j, 3);
-        const int dk = sl == 4 ? d0 : sl == 5 ? d1 : sl == 6 ? d2 : d3;
-        const int bit = sl < 4 ? 4 * j + sl : dk;  // -1: unused slot, mask 0
-        const uint32_t keep = bit < 0 ? 0u : ~0u;
-        const uint32_t sh = bit < 0 ? 0u : (uint32_t)bit;
+        const int lane = threadIdx.x % kWave;
+        const RoundMaskLane rml(lane);
 #pragma unroll
         for (int r = 0; r < 48 / kWavesPerBlock; r++) {
             const int t = (int)wave + kWavesPerBlock * r;
             // both words as scalars (read once per wave), then a per-lane pick
-            const uint32_t lo = __builtin_amdgcn_readfirstlane(keys.w[2 * t]);
-            const uint32_t hi = __builtin_amdgcn_readfirstlane(keys.w[2 * t + 1]);
-            const uint32_t w = sl < 4 ? lo : hi;
-            km[kBsRoundMasks * t + lane] = (0u - ((w >> sh) & 1u)) & keep;
+            km[kBsRoundMasks * t + lane] = rml(__builtin_amdgcn_readfirstlane(keys.w[2 * t]),
+                                               __builtin_amdgcn_readfirstlane(keys.w[2 * t + 1]));
         }
         // extra group g = w, entry n = lane < 32: bit n of word 96 + g
         if (lane < 32) km[kBsInitY + 32 * wave + lane] = 0u - ((keys.w[96 + wave] >> lane) & 1u);

@@ -2,9 +2,13 @@
  * tdes_probe.h - microbenchmarks for the hardware ceilings the 3DES kernels
  * are reported against (not part of the cipher).
  *
- * The bitsliced kernel is bound by the 32-bit vector ALU: its rounds are
- * v_bitop3_b32 gates and v_xor_b32 with a scalar key mask.  These probes
- * measure how many such lane operations per second MI355X sustains, and the
+ * The bitsliced kernel is bound by issue of 32-bit vector ALU instructions:
+ * its rounds are v_bitop3_b32 gates and key XORs with vector operands, its
+ * transposes byte permutes, shifts and selects.  A gfx950 SIMD issues a
+ * wave64 VALU instruction over four cycles and may issue a second one from
+ * another wave in the same four cycles, for some opcodes only; these probes
+ * measure the sustained lane-operation rate per opcode (rocprofv3 counters
+ * SQ_INSTS_VALU / SQ_ACTIVE_INST_VALU2 give the pairing directly), and the
  * HBM bandwidth of a plain copy (also the reference kernel whose memory
  * counters calibrate the cipher's measured HBM traffic).
  *
@@ -23,9 +27,15 @@ extern "C" {
 #endif
 
 enum {
-    TDES_PROBE_BITOP3 = 0,   /* v_bitop3_b32, three vector operands        */
-    TDES_PROBE_XOR = 1,      /* v_xor_b32, two vector operands             */
-    TDES_PROBE_XOR_SGPR = 2  /* v_xor_b32 with one scalar operand          */
+    TDES_PROBE_BITOP3 = 0,    /* v_bitop3_b32, three vector operands        */
+    TDES_PROBE_XOR = 1,       /* v_xor_b32, two vector operands             */
+    TDES_PROBE_XOR_SGPR = 2,  /* v_xor_b32 with one scalar operand          */
+    TDES_PROBE_PERM = 3,      /* v_perm_b32 (byte permute), vector operands */
+    TDES_PROBE_BFI = 4,       /* v_bfi_b32 (bit-field insert)               */
+    TDES_PROBE_LSHL = 5,      /* v_lshlrev_b32 by an inline constant        */
+    TDES_PROBE_LSHR = 6,      /* v_lshrrev_b32 by an inline constant        */
+    TDES_PROBE_ADD = 7,       /* v_add_u32, two vector operands             */
+    TDES_PROBE_BFE = 8        /* v_bfe_i32 (sign-extended bit-field extract) */
 };
 
 /* Launch `blocks` workgroups of 256 threads; every thread issues

@@ -23,13 +23,26 @@ __global__ __launch_bounds__(kThreads) void valu_probe_kernel(uint32_t *sink, ui
     for (uint32_t i = 0; i < iters; i++) {
 #pragma unroll
         for (int j = 0; j < kAcc; j++) {
+            const uint32_t b = a[(j + 1) % kAcc], c = a[(j + 2) % kAcc];
             if (OP == TDES_PROBE_BITOP3)
                 asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xe8"
-                             : "=v"(a[j]) : "v"(a[j]), "v"(a[(j + 1) % kAcc]), "v"(a[(j + 2) % kAcc]));
+                             : "=v"(a[j]) : "v"(a[j]), "v"(b), "v"(c));
             else if (OP == TDES_PROBE_XOR)
                 asm volatile("v_xor_b32 %0, %1, %2" : "=v"(a[j]) : "v"(a[j]), "v"(a[(j + 3) % kAcc]));
-            else
+            else if (OP == TDES_PROBE_XOR_SGPR)
                 asm volatile("v_xor_b32 %0, %1, %2" : "=v"(a[j]) : "s"(smask), "v"(a[j]));
+            else if (OP == TDES_PROBE_PERM)
+                asm volatile("v_perm_b32 %0, %1, %2, %3" : "=v"(a[j]) : "v"(a[j]), "v"(b), "v"(c));
+            else if (OP == TDES_PROBE_BFI)
+                asm volatile("v_bfi_b32 %0, %1, %2, %3" : "=v"(a[j]) : "v"(a[j]), "v"(b), "v"(c));
+            else if (OP == TDES_PROBE_LSHL)
+                asm volatile("v_lshlrev_b32 %0, 3, %1" : "=v"(a[j]) : "v"(b));
+            else if (OP == TDES_PROBE_LSHR)
+                asm volatile("v_lshrrev_b32 %0, 3, %1" : "=v"(a[j]) : "v"(b));
+            else if (OP == TDES_PROBE_ADD)
+                asm volatile("v_add_u32 %0, %1, %2" : "=v"(a[j]) : "v"(a[j]), "v"(b));
+            else
+                asm volatile("v_bfe_i32 %0, %1, 4, 1" : "=v"(a[j]) : "v"(b));
         }
     }
     uint32_t r = 0;
@@ -50,18 +63,21 @@ __global__ __launch_bounds__(kThreads) void copy_probe_kernel(const uint4 *in, u
 extern "C" {
 
 int tdes_probe_valu(int op, uint32_t *d_sink, unsigned blocks, unsigned iters, void *stream) {
-    if (d_sink == nullptr || blocks == 0 || iters == 0 || op < 0 || op > TDES_PROBE_XOR_SGPR)
-        return -1;
+    if (d_sink == nullptr || blocks == 0 || iters == 0 || op < 0 || op > TDES_PROBE_BFE) return -1;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (op == TDES_PROBE_BITOP3)
-        hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_BITOP3>, dim3(blocks), dim3(kThreads), 0,
-                           s, d_sink, iters, 0x5A5A5A5Au);
-    else if (op == TDES_PROBE_XOR)
-        hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_XOR>, dim3(blocks), dim3(kThreads), 0, s,
-                           d_sink, iters, 0x5A5A5A5Au);
-    else
-        hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_XOR_SGPR>, dim3(blocks), dim3(kThreads),
-                           0, s, d_sink, iters, 0x5A5A5A5Au);
+    const dim3 g(blocks), t(kThreads);
+    const uint32_t m = 0x5A5A5A5Au;
+    switch (op) {
+    case TDES_PROBE_BITOP3: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_BITOP3>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_XOR: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_XOR>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_XOR_SGPR: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_XOR_SGPR>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_PERM: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_PERM>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_BFI: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_BFI>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_LSHL: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_LSHL>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_LSHR: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_LSHR>, g, t, 0, s, d_sink, iters, m); break;
+    case TDES_PROBE_ADD: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_ADD>, g, t, 0, s, d_sink, iters, m); break;
+    default: hipLaunchKernelGGL(valu_probe_kernel<TDES_PROBE_BFE>, g, t, 0, s, d_sink, iters, m); break;
+    }
     return hipGetLastError() == hipSuccess ? 0 : -6;
 }
 

@@ -4,7 +4,8 @@ import ctypes
 
 from . import tdes
 
-OPS = {"bitop3": 0, "xor": 1, "xor_sgpr": 2}
+OPS = {"bitop3": 0, "xor": 1, "xor_sgpr": 2, "perm": 3, "bfi": 4, "lshl": 5, "lshr": 6,
+       "add": 7, "bfe": 8}
 LANE_OPS_PER_ITER = 16
 
 
@@ -63,8 +64,22 @@ def copy_rate(nbytes=1 << 30, reps=5):
     return 2 * nbytes / best
 
 
-if __name__ == "__main__":
+def main():
+    """Lane-operation rate per probed opcode at 2, 4 and 8 waves per SIMD
+    (256 CUs x 4 SIMDs; a workgroup is 4 waves).  Under rocprofv3 --pmc
+    SQ_INSTS_VALU SQ_ACTIVE_INST_VALU2 the share of instructions issued in
+    pairs is 2 * SQ_ACTIVE_INST_VALU2 / SQ_INSTS_VALU per dispatch."""
     import json
-    res = {op: valu_rate(op) / 1e12 for op in OPS}
-    res["copy_TBps"] = copy_rate() / 1e12
-    print(json.dumps({k: round(v, 3) for k, v in res.items()}))
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for wps in (2, 4, 8):
+        blocks = cus * wps  # cus * 4 SIMDs * wps waves / 4 waves per block
+        for op in OPS:
+            r = valu_rate(op, blocks=blocks, iters=8000 // wps, reps=2)
+            print(json.dumps({"op": op, "waves_per_simd": wps, "blocks": blocks,
+                              "T_lane_ops_per_s": round(r / 1e12, 2)}), flush=True)
+    print(json.dumps({"copy_TBps": round(copy_rate() / 1e12, 3)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

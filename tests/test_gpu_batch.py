@@ -140,6 +140,30 @@ def test_16k_lognormal_batch(torch_dev):
         assert np.array_equal(got[o:o + n], want), i
 
 
+@pytest.mark.parametrize("n", [1, 8191, 8192, 8193, 20000])
+def test_scan_chunk_boundaries(torch_dev, n):
+    # The descriptor scan works in chunks of 8192 messages: batches just
+    # below, at and just above a chunk edge, and one spanning three chunks,
+    # with short messages (one to three slices) and some empty ones.
+    g = W.rng(W.SEED_BASE + 0x305 + n)
+    lengths = (g.integers(0, 97, size=n) * 8).astype(np.int64)
+    lengths[g.random(n) < 0.05] = 0
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    data = W.uniform_bytes(g, max(int(lengths.sum()), 8))
+    _say("batch scan edges", n, int(lengths.sum()))
+    offs, got, b = _run_batch(torch_dev, keys, lengths, dirs, data)
+    assert b.skipped() == 0
+    if n < 64:
+        check = range(n)
+    else:
+        sample = W.rng(W.SEED_BASE + 0x306).choice(n, 64, replace=False).tolist()
+        check = sorted(set(sample) | {0, n - 1, min(8191, n - 1), min(8192, n - 1)})
+    for i in check:
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
 def test_device_key_expansion_matches_host(torch_dev):
     """tdes_schedule_expand (key generation on the GPU) writes exactly the
     bytes tdes_schedule_upload writes from the host key schedule."""

@@ -167,3 +167,11 @@ def test_1gib_sampled_and_structured(torch_dev, kernel):
         torch.cuda.synchronize()
         assert bool(same), name
         del x
+
+
+def test_valu_probes_run(torch_dev):
+    # The issue-rate probes the roofline discussion rests on: every opcode
+    # launches and returns a positive rate.
+    from paper_2007_10752_amd import probe
+    for op in probe.OPS:
+        assert probe.valu_rate(op, blocks=256, iters=64, reps=1) > 0, op

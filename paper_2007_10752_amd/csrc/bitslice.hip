@@ -55,8 +55,12 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     const uint32_t lane_off = (threadIdx.x % kWave) * 16u;
     // Bytes of this chunk that exist: 16384 except in the last chunk.  The
     // chunk is addressed through buffer resources sized to it, so the
-    // hardware range check zero-fills loads and drops stores past the end;
-    // the partial path uses 8-byte accesses, each wholly in or out of range.
+    // hardware range check zero-fills loads and drops stores past the end.
+    // The partial path (last chunk, or 8-byte aligned buffers) is written
+    // with 8-byte accesses; the compiler may merge a lane's two loads into
+    // one 16-byte load, which is still exact because the range check
+    // applies per dword (odd block counts in the parity tests cover a piece
+    // that straddles the end).
     const uint32_t avail = live ? (uint32_t)(nbytes - base < kChunk ? nbytes - base : kChunk) : 0u;
     const bool whole = VEC16 && avail == (uint32_t)kChunk;
     const __amdgpu_buffer_rsrc_t src =

@@ -46,6 +46,12 @@ constexpr int kBufferFlags = 0x00020000;
 template <bool VEC16>
 __global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
 void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
+    // Issue priority: a new wave's loads, mask expansion and transposes run
+    // at the highest priority and its rounds at the lowest.  The SIMD's
+    // arbiter otherwise favours the older waves, which are in their rounds,
+    // so a new wave reaches its own rounds late and fewer waves are there to
+    // pair instructions (measured: 6-9 % faster).
+    __builtin_amdgcn_s_setprio(3);
     // the wave index is uniform within the wave; say so, so the chunk base
     // and the buffer resources below live in scalar registers
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -125,6 +131,7 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     __builtin_amdgcn_sched_barrier(0);
 
     const uint32_t *kml = km;
+    __builtin_amdgcn_s_setprio(0);
     LdsPipedRounds rr{kml};
     des3_planes(h0, h1, rr);
     __builtin_amdgcn_sched_barrier(0);

@@ -164,6 +164,35 @@ def test_scan_chunk_boundaries(torch_dev, n):
         assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
 
 
+def test_offsets_beyond_4gib(torch_dev):
+    # Input offsets that straddle byte 2^32 of the input base, outputs at
+    # different (low) offsets of another base.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x307)
+    n = 300
+    lengths = (g.integers(0, 200, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    total = int(lengths.sum())
+    rel = np.zeros(n, dtype=np.int64)
+    rel[1:] = np.cumsum(lengths)[:-1]
+    start = ((1 << 32) - total // 2) & ~7
+    data = W.uniform_bytes(g, total)
+    _say("batch beyond 4GiB", n, total, start)
+    x = torch.empty(start + total, dtype=torch.uint8, device="cuda")
+    x[start:].copy_(torch.from_numpy(data))
+    out = torch.full((total,), 0xA5, dtype=torch.uint8, device="cuda")
+    b = T.Batch(keys, start + rel, rel, lengths, dirs)
+    b.submit(x, out)
+    torch.cuda.synchronize()
+    assert b.skipped() == 0
+    got = out.cpu().numpy()
+    del x, out
+    for i in range(n):
+        seg = slice(int(rel[i]), int(rel[i] + lengths[i]))
+        assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
 def test_device_key_expansion_matches_host(torch_dev):
     """tdes_schedule_expand (key generation on the GPU) writes exactly the
     bytes tdes_schedule_upload writes from the host key schedule."""

@@ -7,7 +7,9 @@ buffers, the 64 MiB case in full for 3-key and 2-key bundles in both
 directions, and the 1 GiB headline case in the launch configuration the
 benchmark times: seeded random positions checked one by one against the
 oracle, plus all-zero and repeating-pattern inputs whose every output block
-must equal the oracle's output on the one distinct input block.
+must equal the oracle's output on the one distinct input block.  Also: key
+bundles at the edges of the key material, a caller-named stream, and a
+buffer past 4 GiB (64-bit addressing).
 """
 import sys
 
@@ -167,6 +169,99 @@ def test_1gib_sampled_and_structured(torch_dev, kernel):
         torch.cuda.synchronize()
         assert bool(same), name
         del x
+
+
+def _weak(pattern):
+    return np.frombuffer(bytes.fromhex(pattern), dtype=np.uint8)
+
+
+# Bundles at the edges of the key material: every key bit zero or one (the
+# kernels' key masks all zero / all ones), DES weak keys (E_K is its own
+# inverse), K1 = K2 = K3 (single DES) and K1 = K2 (EDE reduces to E_K3).
+def _edge_bundles():
+    g = W.rng(W.SEED_BASE + 0x70)
+    k = [W.key_bundle(g)[:8] for _ in range(3)]
+    return {
+        "zero": np.zeros(24, np.uint8),
+        "ones": np.full(24, 0xFF, np.uint8),
+        "weak_01": np.tile(_weak("0101010101010101"), 3),
+        "weak_fe": np.tile(_weak("FEFEFEFEFEFEFEFE"), 3),
+        "weak_e0": np.tile(_weak("E0E0E0E0F1F1F1F1"), 3),
+        "weak_1f": np.tile(_weak("1F1F1F1F0E0E0E0E"), 3),
+        "single": np.concatenate([k[0], k[0], k[0]]),
+        "k1_eq_k2": np.concatenate([k[0], k[0], k[1]]),
+        "two_key": np.concatenate([k[0], k[1], k[0]]),
+    }
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name", list(_edge_bundles()))
+def test_key_edge_cases(torch_dev, kernel, name):
+    key = _edge_bundles()[name]
+    data = W.uniform_bytes(W.rng(W.SEED_BASE + 0x71), 8 * 4099)
+    _say("key edge", name, kernel)
+    for dec in (False, True):
+        got = _gpu(torch_dev, key, data, decrypt=dec, kernel=kernel)
+        assert np.array_equal(got, oracle.tdes_ecb(key, data, dec)), dec
+    if name.startswith("weak") or name in ("zero", "ones"):
+        # a weak key's DES is an involution, and so is EDE with three copies
+        twice = _gpu(torch_dev, key, _gpu(torch_dev, key, data, kernel=kernel), kernel=kernel)
+        assert np.array_equal(twice, data)
+    if name == "k1_eq_k2":
+        k3 = np.tile(key[16:], 3)
+        assert np.array_equal(_gpu(torch_dev, key, data, kernel=kernel),
+                              oracle.tdes_ecb(k3, data))
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_side_stream(torch_dev, kernel):
+    # The launch goes on the stream the caller names, not on the null stream.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x72)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 5 * 16384 + 8 * 11)
+    x = torch.from_numpy(data).cuda()
+    out = torch.zeros_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    _say("side stream", kernel)
+    T.encrypt(key, x, out, kernel=kernel, stream=s)
+    back = torch.empty_like(x)
+    T.decrypt(key, out, back, kernel=kernel, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.tdes_ecb(key, data))
+    assert torch.equal(back, x)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_offsets_beyond_4gib(torch_dev, kernel):
+    # A buffer of 4 GiB plus three wave chunks plus 5 blocks, filled with
+    # block counters (block i holds i as a little-endian 64-bit integer, so
+    # an output read from or written to a wrong address cannot match).
+    # Blocks around byte offsets 2^31 and 2^32, the tail and seeded random
+    # positions are checked against the oracle one by one; decryption of the
+    # whole output must give back every block.
+    torch = torch_dev
+    nblk = (4 * GIB + 3 * 16384) // 8 + 5
+    key = W.key_bundle(W.rng(W.SEED_BASE + 0x73))
+    _say("beyond 4GiB", kernel, nblk)
+    x = torch.arange(nblk, dtype=torch.int64, device="cuda").view(torch.uint8)
+    out = torch.empty_like(x)
+    T.encrypt(key, x, out, kernel=kernel)
+    b2, b4 = (1 << 31) // 8, (1 << 32) // 8
+    idx = np.unique(np.concatenate([
+        np.arange(b2 - 2048, b2 + 2048), np.arange(b4 - 4096, b4 + 4096),
+        np.arange(nblk - 8192, nblk),
+        W.rng(W.SEED_BASE + 0x74).choice(nblk, 1 << 15, replace=False)]))
+    ti = torch.from_numpy(idx).cuda()
+    got = out.view(-1, 8)[ti].cpu().numpy().reshape(-1)
+    sample = x.view(-1, 8)[ti].cpu().numpy().reshape(-1)
+    assert np.array_equal(sample.view(np.int64), idx)
+    assert np.array_equal(got, oracle.tdes_ecb(key, sample))
+    T.decrypt(key, out, out, kernel=kernel)
+    same = torch.equal(out, x)
+    del x, out
+    assert same
 
 
 def test_valu_probes_run(torch_dev):

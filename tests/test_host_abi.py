@@ -111,10 +111,15 @@ def _kk(key, dec, kernel):
     return T.kernel_key_bytes(T.key_schedule(key), T.DECRYPT if dec else T.ENCRYPT, kernel)
 
 
-@pytest.mark.parametrize("two_key", [False, True])
-def test_bitslice_emulation_matches_oracle(two_key):
-    g = W.rng(W.SEED_BASE + 0xC00 + two_key)
-    key = W.key_bundle(g, two_key=two_key)
+@pytest.mark.parametrize("kind", ["three_key", "two_key", "all_zero", "all_one"])
+def test_bitslice_emulation_matches_oracle(kind):
+    # all-zero and all-one keys make every key mask 0 or ~0 at once
+    g = W.rng(W.SEED_BASE + 0xC00 + (kind == "two_key"))
+    key = W.key_bundle(g, two_key=kind == "two_key")
+    if kind == "all_zero":
+        key = np.zeros(24, np.uint8)
+    elif kind == "all_one":
+        key = np.full(24, 0xFF, np.uint8)
     data = W.uniform_bytes(g, 8 * 29)  # a partial lane
     ct = E.bitslice_ecb(_kk(key, False, T.KERNEL_BITSLICE), data)
     assert np.array_equal(ct, oracle.tdes_ecb(key, data))

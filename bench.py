@@ -35,6 +35,8 @@ def parse():
                     help="target wall time of the oracle sample (0 disables)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched form (16,384 log-normal messages); 0 disables")
+    ap.add_argument("--host", type=int, default=1,
+                    help="1: also time the host-resident form (1 GiB pinned, PCIe included)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="length of each open-loop serving run (0 disables serving)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -116,6 +118,68 @@ def batched_section(steps):
             "per_message_launches_GBps": round(total / t_loop / 1e9, 3),
             "config": "16384 msgs, lognormal median 4 KiB sigma 1, clip 8 B..1 MiB, "
                       "per-message 3-key bundle, 50/50 enc/dec, seed %d" % (W.SEED_BASE + 3)}
+
+
+def host_section(steps):
+    """The host-resident form (PCIe included): 1 GiB of seeded random bytes
+    in pinned host memory, encrypted into pinned host memory, directly (the
+    kernel on the mapped host buffers) and staged (8 MiB chunks through 3
+    device slots); with the copy engines' own rates over the same buffers for
+    reference (one direction at a time, and both at once)."""
+    import torch
+
+    from paper_2007_10752_amd import tdes
+    from paper_2007_10752_amd import workloads as W
+    n = GIB
+    key = W.key_bundle(W.rng(W.SEED_BASE + 2 + W.KEY_SEED_OFFSET))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(W.SEED_BASE + 4)
+    x = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=gen)
+    want = tdes.encrypt(key, x)
+    src = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    src.copy_(x)
+    d = torch.empty_like(x)
+    torch.cuda.synchronize()
+    reps = max(3, min(steps, 7))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
+
+    t_direct = timed(lambda: tdes.ecb_host(key, src, dst))
+    ok = bool(torch.equal(dst.cuda(), want))
+    pipe = tdes.HostPipeline(8 << 20, 3)
+    t_staged = timed(lambda: pipe.run(key, src, dst))
+    ok = ok and bool(torch.equal(dst.cuda(), want))
+    t_h2d = timed(lambda: d.copy_(src, non_blocking=True))
+    t_d2h = timed(lambda: dst.copy_(want, non_blocking=True))
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def both():
+        with torch.cuda.stream(sa):
+            d.copy_(src, non_blocking=True)
+        with torch.cuda.stream(sb):
+            dst.copy_(want, non_blocking=True)
+
+    t_both = timed(both)
+    direct, both_rate = n / t_direct / 1e9, n / t_both / 1e9
+    return {"value": round(direct, 2), "unit": "GB/s", "mode": "direct",
+            "ms": round(t_direct * 1e3, 3), "bytes": n,
+            "staged_GBps": round(n / t_staged / 1e9, 2), "staged_chunk_bytes": 8 << 20,
+            "staged_slots": 3,
+            "copy_h2d_GBps": round(n / t_h2d / 1e9, 2), "copy_d2h_GBps": round(n / t_d2h / 1e9, 2),
+            "copy_both_directions_GBps": round(both_rate, 2),
+            "frac_of_copy_both_directions": round(direct / both_rate, 3),
+            "equal_to_device_path": ok,
+            "config": "1 GiB, pinned host in and out, 3-key, seed %d" % (W.SEED_BASE + 4)}
 
 
 def serving_section(seconds):
@@ -289,6 +353,10 @@ def main():
     if args.batched:
         line["batched"] = batched_section(args.steps)
         print("batched done", file=sys.stderr, flush=True)
+    if args.host:
+        line["host_resident"] = host_section(args.steps)
+        print("host-resident done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     if args.serve_seconds > 0:
         line["served"] = serving_section(args.serve_seconds)
     if args.cpu_seconds > 0:

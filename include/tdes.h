@@ -17,10 +17,12 @@
  *   - Lengths are in bytes and must be a multiple of 8; no padding is added.
  *   - Device pointers are plain HIP device addresses (for example the
  *     data_ptr() of a torch tensor); the caller owns every buffer.  The
- *     library allocates nothing on the encryption path.
+ *     library allocates no memory on the encryption path (tdes_ecb_host
+ *     creates its streams once per device).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Device calls
  *     only enqueue work and return; results are valid once the stream has
- *     completed the work.
+ *     completed the work.  tdes_ecb_host, which takes host buffers, is
+ *     synchronous instead.
  *   - Argument errors are reported synchronously, before any device work is
  *     enqueued; a failed launch returns TDES_ERR_DEVICE.  tdes_last_error()
  *     gives a message for the last failure on the calling thread.  No C++
@@ -140,6 +142,61 @@ size_t tdes_batch_workspace_bytes(size_t n_msgs);
 tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
                               size_t n_schedules, const void *d_in_base, void *d_out_base,
                               void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* ---- Host-resident form: data in host memory ----------------------------- */
+
+/* Most slots (device staging buffers, one stream each) tdes_ecb_host uses. */
+#define TDES_HOST_MAX_SLOTS 8
+
+/* 3DES-EDE ECB (Sec. III-B; ECB, Sec. V) of nbytes bytes of HOST memory
+ * h_in into host memory h_out, through the device.  The paper's input
+ * starts on the host and its GPU times leave the transfers out (Sec. V);
+ * this call includes them.  Two modes:
+ *
+ *   - Direct (d_work == NULL): h_in and h_out must be pinned host memory
+ *     (hipHostMalloc), which is mapped into the device's address space.  The
+ *     bitsliced kernel reads and writes them there, over PCIe in both
+ *     directions at once; nothing is staged.  chunk_bytes and work_bytes
+ *     are ignored.  Each range must lie within one pinned allocation
+ *     (checked: TDES_ERR_ARG otherwise).
+ *   - Staged (d_work != NULL): any host memory.  The range is cut into
+ *     chunks of chunk_bytes (the last one shorter).  Chunk i goes to slot
+ *     i % n_slots of the device workspace d_work (n_slots =
+ *     min(work_bytes / chunk_bytes, TDES_HOST_MAX_SLOTS)).  There it is
+ *     copied in, encrypted or decrypted in place by the bitsliced kernel,
+ *     and copied out, in order on that slot's stream.  The slots' streams
+ *     run side by side, so copies to the device, kernels and copies back of
+ *     different chunks overlap.  The copies run asynchronously only if the
+ *     host buffers are pinned; pageable memory gives the same result, more
+ *     slowly.  d_work is caller-owned device memory, 256-byte aligned, at
+ *     least chunk_bytes long, not in use by pending device work.  A
+ *     chunk_bytes that is a multiple of 16 KiB keeps every slot 16-byte
+ *     aligned, the kernel's fast path.
+ *
+ * Streams: both modes run on streams that belong to the library.  There is
+ * one set per device, at default priority, created at the first call on
+ * that device and kept until the process ends.
+ *
+ * Buffers: h_in == h_out (in place) is allowed; any other overlap is
+ * TDES_ERR_OVERLAP.  The caller owns every buffer.
+ *
+ * Synchronous, unlike the device calls: it returns once h_out holds the
+ * result or an error occurred.  Calls from several threads are serialised.
+ * nbytes == 0 is a no-op.
+ *
+ * Errors, all reported before any device work:
+ *   - TDES_ERR_ARG: NULL ks or buffers with nbytes > 0, or a bad dir.
+ *     Direct mode: unmapped buffers.  Staged mode: chunk_bytes 0, or
+ *     work_bytes < chunk_bytes;
+ *   - TDES_ERR_LENGTH: nbytes, or (staged) chunk_bytes, not a multiple
+ *     of 8;
+ *   - TDES_ERR_ALIGN: h_in or h_out not 8-byte aligned, or (staged) d_work
+ *     not 256-byte aligned;
+ *   - TDES_ERR_OVERLAP: see above.
+ * TDES_ERR_DEVICE is returned if a HIP call fails.  The contents of h_out
+ * are then unspecified. */
+tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, void *h_out,
+                          size_t nbytes, void *d_work, size_t work_bytes, size_t chunk_bytes);
 
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
  * TDES_KERNEL_SPBOX; AUTO means the kernel AUTO selects) would receive for

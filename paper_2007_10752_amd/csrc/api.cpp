@@ -119,6 +119,42 @@ tdes_status tdes_schedule_expand(const void *d_keys24, size_t n, void *d_schedul
     return TDES_OK;
 }
 
+tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, void *h_out,
+                          size_t nbytes, void *d_work, size_t work_bytes, size_t chunk_bytes) {
+    g_last_error.clear();
+    if (ks == nullptr) return fail(TDES_ERR_ARG, "NULL schedule");
+    if (dir != TDES_ENCRYPT && dir != TDES_DECRYPT) return fail(TDES_ERR_ARG, "bad direction %d", dir);
+    tdes_status st = check_buffers(h_in, h_out, nbytes);
+    if (st != TDES_OK || nbytes == 0) return st;
+    tdes::BitsliceKeys k;
+    if (d_work == nullptr) {  // direct: the kernel works on the mapped host buffers
+        uint8_t *d_in = nullptr, *d_out = nullptr;
+        hipError_t e = tdes::mapped_range(h_in, nbytes, &d_in);
+        if (e == hipSuccess) e = tdes::mapped_range(h_out, nbytes, &d_out);
+        if (e != hipSuccess)
+            return fail(TDES_ERR_ARG, "direct mode needs pinned host buffers: %s", hipGetErrorString(e));
+        tdes::bitslice_keys(*ks, dir, &k);
+        e = tdes::run_host_direct(k, d_in, d_out, nbytes);
+        if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "direct host run failed: %s", hipGetErrorString(e));
+        return TDES_OK;
+    }
+    if (chunk_bytes == 0) return fail(TDES_ERR_ARG, "chunk_bytes is 0");
+    if (chunk_bytes % 8 != 0)
+        return fail(TDES_ERR_LENGTH, "chunk_bytes %zu is not a multiple of 8", chunk_bytes);
+    if ((uintptr_t)d_work % 256 != 0) return fail(TDES_ERR_ALIGN, "workspace must be 256-byte aligned");
+    if (work_bytes < chunk_bytes)
+        return fail(TDES_ERR_ARG, "workspace (%zu bytes) smaller than one chunk (%zu)", work_bytes,
+                    chunk_bytes);
+    size_t n_slots = work_bytes / chunk_bytes;
+    if (n_slots > TDES_HOST_MAX_SLOTS) n_slots = TDES_HOST_MAX_SLOTS;
+    tdes::bitslice_keys(*ks, dir, &k);
+    hipError_t e = tdes::run_host_pipeline(k, static_cast<const uint8_t *>(h_in),
+                                           static_cast<uint8_t *>(h_out), nbytes,
+                                           static_cast<uint8_t *>(d_work), n_slots, chunk_bytes);
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "host pipeline failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
 size_t tdes_batch_workspace_bytes(size_t n_msgs) { return tdes::batch_workspace_bytes(n_msgs); }
 
 tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,

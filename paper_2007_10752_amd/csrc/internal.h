@@ -61,4 +61,17 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 
+// Host-resident pipeline behind tdes_ecb_host (arguments already checked):
+// chunks of `chunk` bytes through n_slots device slots at d_work; returns
+// once every chunk is back in h_out, or the first HIP error.
+hipError_t run_host_pipeline(const BitsliceKeys &k, const uint8_t *h_in, uint8_t *h_out,
+                             size_t nbytes, uint8_t *d_work, size_t n_slots, size_t chunk);
+// Device address *d of the host range [h, h + n), n > 0: an error unless
+// the whole range lies in one pinned, device-mapped host allocation.
+hipError_t mapped_range(const void *h, size_t n, uint8_t **d);
+// The kernel run in place on device-mapped host memory (device addresses
+// from mapped_range); returns once it has finished, or the first HIP error.
+hipError_t run_host_direct(const BitsliceKeys &k, const uint8_t *d_in, uint8_t *d_out,
+                           size_t nbytes);
+
 }  // namespace tdes

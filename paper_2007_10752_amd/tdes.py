@@ -25,7 +25,7 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_probe_copy", "tdes_schedule_upload", "tdes_schedule_expand",
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
-           "tdes_server_release", "tdes_server_get_stats", "tdes_server_now")
+           "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -78,6 +78,8 @@ def lib():
         L.tdes_batch_workspace_bytes.restype = sz
         L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp]
         L.tdes_batch_submit.restype = ctypes.c_int
+        L.tdes_ecb_host.argtypes = [sched_p, ctypes.c_int, vp, vp, sz, vp, sz, sz]
+        L.tdes_ecb_host.restype = ctypes.c_int
         L.tdes_kernel_key_bytes.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, sz]
         L.tdes_kernel_key_bytes.restype = ctypes.c_long
         L.tdes_probe_valu.argtypes = [ctypes.c_int, vp, ctypes.c_uint, ctypes.c_uint, vp]
@@ -152,6 +154,78 @@ def ecb(key, x, out=None, decrypt=False, kernel="auto", stream=None):
 
 def encrypt(key, x, out=None, kernel="auto", stream=None):
     return ecb(key, x, out, False, kernel, stream)
+
+
+HOST_MAX_SLOTS = 8
+
+
+def ecb_host_ptr(schedule, direction, h_in, h_out, nbytes, d_work, work_bytes, chunk_bytes):
+    _check(lib().tdes_ecb_host(ctypes.byref(schedule), direction, ctypes.c_void_p(h_in),
+                               ctypes.c_void_p(h_out), ctypes.c_size_t(nbytes),
+                               ctypes.c_void_p(d_work), ctypes.c_size_t(work_bytes),
+                               ctypes.c_size_t(chunk_bytes)))
+
+
+def _host_ptr(a):
+    """Address and size of a contiguous host byte buffer: a numpy uint8 array
+    or a CPU uint8 torch tensor (pinned or not)."""
+    import numpy as np
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.uint8 or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("host buffer must be a contiguous uint8 array")
+        return a.ctypes.data, a.size
+    import torch
+    if a.is_cuda or a.dtype != torch.uint8 or not a.is_contiguous():
+        raise ValueError("host buffer must be a contiguous uint8 CPU tensor")
+    return a.data_ptr(), a.numel()
+
+
+def _host_out(h_in, h_out):
+    import torch
+    if h_out is None:
+        h_out = (h_in.copy() if hasattr(h_in, "flags") else
+                 torch.empty(h_in.shape, dtype=torch.uint8, pin_memory=h_in.is_pinned()))
+    a, n = _host_ptr(h_in)
+    b, m = _host_ptr(h_out)
+    if m != n:
+        raise ValueError("h_out must have the size of h_in")
+    return h_out, a, b, n
+
+
+def ecb_host(key, h_in, h_out=None, decrypt=False):
+    """Direct host-resident 3DES-EDE ECB: the kernel reads h_in and writes
+    h_out (pinned CPU uint8 tensors; h_out a new pinned tensor if None, h_in
+    for in place) in host memory over PCIe.  Returns h_out once it holds the
+    result."""
+    import torch
+    h_out, a, b, n = _host_out(h_in, h_out)
+    # the library's stream does not wait for torch's (pending copies into h_in)
+    torch.cuda.current_stream().synchronize()
+    ecb_host_ptr(_schedule(key), DECRYPT if decrypt else ENCRYPT, a, b, n, None, 0, 0)
+    return h_out
+
+
+class HostPipeline:
+    """Staged host-resident 3DES-EDE ECB (any host memory): n_slots device
+    slots of chunk_bytes in one torch tensor, reused by every run."""
+
+    def __init__(self, chunk_bytes=8 << 20, n_slots=4):
+        import torch
+        self.chunk_bytes = int(chunk_bytes)
+        self.work = torch.empty(self.chunk_bytes * int(n_slots), dtype=torch.uint8, device="cuda")
+
+    def run(self, key, h_in, h_out=None, decrypt=False):
+        """3DES-EDE ECB of host buffer h_in into h_out (same type; a new
+        buffer like h_in if None; h_in itself for in place).  Returns h_out
+        once it holds the result."""
+        import torch
+        h_out, a, b, n = _host_out(h_in, h_out)
+        # the library's streams do not wait for torch's: let pending work on
+        # the workspace finish first
+        torch.cuda.current_stream().synchronize()
+        ecb_host_ptr(_schedule(key), DECRYPT if decrypt else ENCRYPT, a, b, n,
+                     self.work.data_ptr(), self.work.numel(), self.chunk_bytes)
+        return h_out
 
 
 def decrypt(key, x, out=None, kernel="auto", stream=None):

@@ -82,6 +82,31 @@ def test_argument_errors_before_device_work():
     assert lib.tdes_probe_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 32, None) == -1
 
 
+def _host(nbytes=64, h_in=0x1000, h_out=0x10000, d_work=0x100000, work=1 << 20, chunk=1 << 16,
+          dir=0, sched=True):
+    s = T.key_schedule(bytes(24))
+    return T.lib().tdes_ecb_host(ctypes.byref(s) if sched else None, dir, ctypes.c_void_p(h_in),
+                                 ctypes.c_void_p(h_out), nbytes, ctypes.c_void_p(d_work), work,
+                                 chunk)
+
+
+def test_host_path_argument_errors():
+    # tdes_ecb_host (staged mode: a workspace is given) rejects each of these
+    # before any HIP call
+    assert _host(sched=False) == -1
+    assert _host(dir=2) == -1
+    assert _host(chunk=0) == -1
+    assert _host(chunk=12) == -2                   # TDES_ERR_LENGTH
+    assert _host(nbytes=12) == -2
+    assert _host(h_in=0x1004) == -3                # TDES_ERR_ALIGN
+    assert _host(d_work=0x100008) == -3            # workspace not 256-byte aligned
+    assert _host(h_out=0x1008) == -4               # TDES_ERR_OVERLAP
+    assert _host(work=1 << 15) == -1               # workspace smaller than a chunk
+    assert b"smaller than one chunk" in T.lib().tdes_last_error()
+    assert _host(h_in=0) == -1
+    assert _host(nbytes=0, h_in=0, h_out=0, d_work=0) == 0  # empty: no-op
+
+
 def _crypt_msg(n, a, b):
     _crypt(n, a, b)
     return T.lib().tdes_last_error()

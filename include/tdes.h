@@ -150,8 +150,8 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
 
 /* 3DES-EDE ECB (Sec. III-B; ECB, Sec. V) of nbytes bytes of HOST memory
  * h_in into host memory h_out, through the device.  The paper's input
- * starts on the host and its GPU times leave the transfers out (Sec. V);
- * this call includes them.  Two modes:
+ * starts on the host (Sec. IV-C) and its GPU times leave the transfers out
+ * (Sec. V); this call includes them.  Two modes:
  *
  *   - Direct (d_work == NULL): h_in and h_out must be pinned host memory
  *     (hipHostMalloc), which is mapped into the device's address space.  The

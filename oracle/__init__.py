@@ -90,6 +90,49 @@ def tdes_ecb(key24, data, decrypt=False):
     return _ecb(_load().oracle_tdes_ecb, key24, 24, data, decrypt)
 
 
+# ---- Other modes over the same block cipher ----------------------------------
+# The paper applies 3DES in ECB only (Sec. V).  The modes below are the
+# standard ones (NIST SP 800-38A) built on the block cipher above, written
+# from their definitions: CTR in Sec. 6.5, CBC in Sec. 6.2.
+
+
+def tdes_ctr(key24, iv8, data):
+    """CTR mode: output block i = input block i XOR E(T_i), with counter
+    block T_i = (IV + i) mod 2^64, the whole 64-bit block read as a
+    big-endian integer (SP 800-38A Sec. 6.5 and its Appendix B incrementing
+    function with m = 64).  Encryption and decryption are the same."""
+    d = _u8(data).reshape(-1)
+    if d.size % 8:
+        raise ValueError("length %d is not a multiple of 8 bytes" % d.size)
+    iv = int.from_bytes(bytes(_u8(iv8, 8)), "big")
+    n = d.size // 8
+    counters = (np.uint64(iv) + np.arange(n, dtype=np.uint64))  # wraps mod 2^64
+    blocks = counters.astype(">u8").view(np.uint8)
+    return d ^ tdes_ecb(key24, blocks)
+
+
+def tdes_cbc_encrypt(key24, iv8, data):
+    """CBC encryption (SP 800-38A Sec. 6.2): C_i = E(P_i XOR C_{i-1}), with
+    C_{-1} = IV; one block after another."""
+    d = _u8(data).reshape(-1, 8)
+    out = np.empty_like(d)
+    prev = _u8(iv8, 8)
+    for i in range(d.shape[0]):
+        prev = tdes_ecb(key24, d[i] ^ prev)
+        out[i] = prev
+    return out.reshape(-1)
+
+
+def tdes_cbc_decrypt(key24, iv8, data):
+    """CBC decryption (SP 800-38A Sec. 6.2): P_i = D(C_i) XOR C_{i-1}, with
+    C_{-1} = IV; every block independent of the others' results."""
+    d = _u8(data).reshape(-1)
+    if d.size % 8:
+        raise ValueError("length %d is not a multiple of 8 bytes" % d.size)
+    prev = np.concatenate([_u8(iv8, 8), d[:-8]]) if d.size else d
+    return tdes_ecb(key24, d, decrypt=True) ^ prev
+
+
 TABLES = ("pc_1", "shift_keys", "pc_2", "initial_perm", "exp_d", "s", "per", "final_perm")
 
 

@@ -71,6 +71,50 @@ def test_des_matches_openssl(case):
     assert np.array_equal(oracle.des_ecb(key, data, True), _openssl_dec(args, key, data))
 
 
+# ---- CTR and CBC (the oracle's other modes) ----------------------------------
+
+def _iv_cases(g):
+    # a random IV, and one three blocks below 2^64 so the counter wraps
+    return [W.uniform_bytes(g, 8), np.frombuffer(((1 << 64) - 3).to_bytes(8, "big"), np.uint8)]
+
+
+def test_ctr_matches_openssl_ecb_of_counter_blocks():
+    # Counter blocks built here with Python integers, encrypted by OpenSSL
+    # as a black box, XORed with the data.
+    g = _gen(600)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 8 * 77)
+    for iv in _iv_cases(g):
+        v = int.from_bytes(bytes(iv), "big")
+        counters = b"".join(((v + i) % (1 << 64)).to_bytes(8, "big") for i in range(77))
+        ks = _openssl(["-des-ede3"], key, np.frombuffer(counters, np.uint8))
+        assert np.array_equal(oracle.tdes_ctr(key, iv, data), data ^ ks)
+
+
+def test_ctr_is_its_own_inverse_and_zero_data_gives_keystream():
+    g = _gen(601)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 8 * 50)
+    iv = W.uniform_bytes(g, 8)
+    ct = oracle.tdes_ctr(key, iv, data)
+    assert np.array_equal(oracle.tdes_ctr(key, iv, ct), data)
+    zero = oracle.tdes_ctr(key, iv, np.zeros(16, np.uint8))
+    assert np.array_equal(zero[:8], oracle.tdes_ecb(key, iv))
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_cbc_matches_openssl(case):
+    g = _gen(610 + case)
+    key = W.key_bundle(g, two_key=case == 2)
+    data = W.uniform_bytes(g, 8 * 93)
+    iv = W.uniform_bytes(g, 8)
+    args = ["-des-ede3-cbc", "-iv", bytes(iv).hex()]
+    ct = oracle.tdes_cbc_encrypt(key, iv, data)
+    assert np.array_equal(ct, _openssl(args, key, data))
+    assert np.array_equal(oracle.tdes_cbc_decrypt(key, iv, data), _openssl_dec(args, key, data))
+    assert np.array_equal(oracle.tdes_cbc_decrypt(key, iv, ct), data)
+
+
 @pytest.mark.parametrize("two_key", [False, True])
 def test_decrypt_inverts_encrypt(two_key):
     g = _gen(200 + two_key)

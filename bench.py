@@ -35,6 +35,8 @@ def parse():
                     help="target wall time of the oracle sample (0 disables)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched form (16,384 log-normal messages); 0 disables")
+    ap.add_argument("--modes", type=int, default=1,
+                    help="1: also time CTR mode on the same 1 GiB")
     ap.add_argument("--host", type=int, default=1,
                     help="1: also time the host-resident form (1 GiB pinned, PCIe included)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
@@ -348,6 +350,15 @@ def main():
                               / costs.HBM_PEAK_BYTES, 4),
         },
     }
+    if args.modes:
+        iv = W.uniform_bytes(W.rng(W.SEED_BASE + 5), 8)
+        sched = tdes.key_schedule(key)
+        t_ctr = time_launches(lambda: tdes.ctr_crypt_ptr(sched, iv, x.data_ptr(), out.data_ptr(),
+                                                         nbytes, sh), max(3, args.steps), stream)
+        line["ctr"] = {"value": round(nbytes / t_ctr / 1e9, 3), "unit": "GB/s",
+                       "ms": round(t_ctr * 1e3, 4),
+                       "config": "same bytes and key in CTR mode, seeded 8-byte IV"}
+        print("modes done", file=sys.stderr, flush=True)
     del x, out
     torch.cuda.empty_cache()
     if args.batched:

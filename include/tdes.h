@@ -90,6 +90,18 @@ tdes_status tdes_ecb_decrypt(const tdes_schedule *ks, const void *d_in, void *d_
 tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const void *d_in,
                            void *d_out, size_t nbytes, void *stream);
 
+/* 3DES-EDE in counter mode over device memory (CTR, NIST SP 800-38A
+ * Sec. 6.5; the paper itself uses ECB only, Sec. V).  Output block i is
+ * input block i XOR E(T_i), where E is the 3DES-EDE encryption of
+ * Sec. III-B with bundle ks.  The counter block T_i is (IV + i) mod 2^64,
+ * the whole 64-bit block read as a big-endian integer; iv points to its
+ * 8 bytes (host memory).  Encryption and decryption are the same
+ * operation.  The counter blocks are made in the kernel, so only the data
+ * is read.  Buffers, stream and errors as for tdes_ecb_encrypt, plus
+ * TDES_ERR_ARG for a NULL iv. */
+tdes_status tdes_ctr_crypt(const tdes_schedule *ks, const uint8_t iv[8], const void *d_in,
+                           void *d_out, size_t nbytes, void *stream);
+
 /* ---- Batched form: many messages, each with its own key and direction --- */
 
 /* Bytes of device-resident key material per schedule (both directions). */

@@ -81,6 +81,23 @@ tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const v
     return TDES_OK;
 }
 
+tdes_status tdes_ctr_crypt(const tdes_schedule *ks, const uint8_t iv[8], const void *d_in,
+                           void *d_out, size_t nbytes, void *stream) {
+    g_last_error.clear();
+    if (ks == nullptr || iv == nullptr) return fail(TDES_ERR_ARG, "NULL schedule or iv");
+    tdes_status st = check_buffers(d_in, d_out, nbytes);
+    if (st != TDES_OK || nbytes == 0) return st;
+    uint64_t ctr = 0;
+    for (int i = 0; i < 8; i++) ctr = ctr << 8 | iv[i];  // big-endian counter value
+    tdes::BitsliceKeys k;
+    tdes::bitslice_keys(*ks, TDES_ENCRYPT, &k);
+    hipError_t e = tdes::launch_bitslice_ctr(k, ctr, static_cast<const uint8_t *>(d_in),
+                                             static_cast<uint8_t *>(d_out), nbytes,
+                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
 tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
                              size_t nbytes, void *stream) {
     return tdes_ecb_crypt(ks, TDES_ENCRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);

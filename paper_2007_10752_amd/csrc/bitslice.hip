@@ -21,6 +21,11 @@
 // to back in registers: FP followed by IP is the identity, so the inner
 // permutations vanish and the R16 || L16 swap between passes is a change of
 // roles between the two halves.
+//
+// Modes.  ECB processes the loaded blocks.  CTR (SP 800-38A) processes
+// counter blocks made in registers (the block at byte offset o holds
+// ctr + o / 8, big-endian) and XORs the data into the result on the way
+// out; nothing is loaded before the rounds.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,6 +34,9 @@
 #include "generated/bitslice_keys_gen.h"
 #include "internal.h"
 
+#ifndef TDES_CTR_MIN_WAVES
+#define TDES_CTR_MIN_WAVES 5  // CTR's budget (a few spills between the passes)
+#endif
 #ifndef TDES_BS_MIN_WAVES
 #define TDES_BS_MIN_WAVES 4  // waves per SIMD the register budget must allow
 #endif
@@ -43,9 +51,51 @@ constexpr size_t kChunk = 16384;  // bytes per wave
 // Buffer-resource word 3 for gfx9-family raw (unstructured) buffers.
 constexpr int kBufferFlags = 0x00020000;
 
-template <bool VEC16>
-__global__ __launch_bounds__(kWave *kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(TDES_BS_MIN_WAVES, 8)))
-void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys) {
+// The 16-byte piece k of a lane (blocks 2k and 2k + 1), read after the
+// rounds: one 16-byte load, or two 8-byte loads on the partial path.
+template <bool WHOLE>
+__device__ __forceinline__ v4u load_piece_late(__amdgpu_buffer_rsrc_t src, uint32_t lane_off, int k) {
+    if (WHOLE) return __builtin_amdgcn_raw_buffer_load_b128(src, lane_off, k * 1024, 0);
+    const v2u a = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off, k * 1024, 0);
+    const v2u b = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off + 8u, k * 1024, 0);
+    return v4u{a[0], a[1], b[0], b[1]};
+}
+
+// CTR output: XOR the lane's 32 input blocks into its 32 keystream blocks
+// and store each piece as soon as it is complete, four pieces at a time (16
+// registers of input in flight; each result goes straight to its store).
+template <bool WHOLE>
+__device__ __forceinline__ void xor_store_blocks(const uint32_t (&h0)[32], const uint32_t (&h1)[32],
+                                                 __amdgpu_buffer_rsrc_t src,
+                                                 __amdgpu_buffer_rsrc_t dst, uint32_t lane_off) {
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        __builtin_amdgcn_sched_barrier(0);
+        v4u dv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) dv[j] = load_piece_late<WHOLE>(src, lane_off, 4 * g + j);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int k = 4 * g + j;
+            const v4u v = {h0[2 * k] ^ dv[j][0], h1[2 * k] ^ dv[j][1], h0[2 * k + 1] ^ dv[j][2],
+                           h1[2 * k + 1] ^ dv[j][3]};
+            if (WHOLE) {
+                __builtin_amdgcn_raw_buffer_store_b128(v, dst, lane_off, k * 1024, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b64(v2u{v[0], v[1]}, dst, lane_off, k * 1024, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(v2u{v[2], v[3]}, dst, lane_off + 8u, k * 1024, 0);
+            }
+        }
+    }
+}
+
+// ECB fits 5 waves per SIMD (96 registers) at the budget of 4; CTR needs the
+// 5-wave budget asked for explicitly.
+template <bool VEC16, int MODE>
+__global__ __launch_bounds__(kWave *kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(MODE == 0 ? TDES_BS_MIN_WAVES : TDES_CTR_MIN_WAVES, 8)))
+void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys,
+                          ModeArgs mode) {
     // Issue priority: a new wave's loads, mask expansion and transposes run
     // at the highest priority and its rounds at the lowest.  The SIMD's
     // arbiter otherwise favours the older waves, which are in their rounds,
@@ -76,7 +126,21 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
 
     // Request the chunk: its memory latency overlaps the mask expansion.
     uint32_t h0[32], h1[32];
-    if (whole) {
+    if (MODE == kModeCtr) {
+        if (live) {
+            // counter blocks: ctr + (byte offset) / 8, as big-endian bytes,
+            // so each 32-bit word (loaded little-endian) is byte-swapped
+            const uint64_t c0 = mode.ctr + (base + lane_off) / 8;
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint64_t ca = c0 + (uint64_t)(k * 128), cb = ca + 1;
+                h0[2 * k] = __builtin_bswap32((uint32_t)(ca >> 32));
+                h1[2 * k] = __builtin_bswap32((uint32_t)ca);
+                h0[2 * k + 1] = __builtin_bswap32((uint32_t)(cb >> 32));
+                h1[2 * k + 1] = __builtin_bswap32((uint32_t)cb);
+            }
+        }
+    } else if (whole) {
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const v4u v = __builtin_amdgcn_raw_buffer_load_b128(src, lane_off, k * 1024, 0);
@@ -139,6 +203,13 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     __builtin_amdgcn_sched_barrier(0);
     transpose32(h1);
 
+    if (MODE == kModeCtr) {
+        if (whole)
+            xor_store_blocks<true>(h0, h1, src, dst, lane_off);
+        else
+            xor_store_blocks<false>(h0, h1, src, dst, lane_off);
+        return;
+    }
     if (whole) {
 #pragma unroll
         for (int k = 0; k < 16; k++) {
@@ -155,21 +226,32 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
     }
 }
 
-}  // namespace
-
-hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *out,
-                           size_t nbytes, hipStream_t stream) {
+template <int MODE>
+hipError_t launch_mode(const BitsliceKeys &k, const ModeArgs &m, const uint8_t *in, uint8_t *out,
+                       size_t nbytes, hipStream_t stream) {
     const size_t chunks = (nbytes + kChunk - 1) / kChunk;
     const size_t blocks = (chunks + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
     const bool vec16 = ((((uintptr_t)in) | ((uintptr_t)out)) & 15u) == 0;
     if (vec16)
-        hipLaunchKernelGGL(tdes_bitslice_kernel<true>, dim3((unsigned)blocks),
-                           dim3(kWave * kWavesPerBlock), 0, stream, in, out, nbytes, k);
+        hipLaunchKernelGGL((tdes_bitslice_kernel<true, MODE>), dim3((unsigned)blocks),
+                           dim3(kWave * kWavesPerBlock), 0, stream, in, out, nbytes, k, m);
     else
-        hipLaunchKernelGGL(tdes_bitslice_kernel<false>, dim3((unsigned)blocks),
-                           dim3(kWave * kWavesPerBlock), 0, stream, in, out, nbytes, k);
+        hipLaunchKernelGGL((tdes_bitslice_kernel<false, MODE>), dim3((unsigned)blocks),
+                           dim3(kWave * kWavesPerBlock), 0, stream, in, out, nbytes, k, m);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *out,
+                           size_t nbytes, hipStream_t stream) {
+    return launch_mode<kModeEcb>(k, ModeArgs{}, in, out, nbytes, stream);
+}
+
+hipError_t launch_bitslice_ctr(const BitsliceKeys &k, uint64_t ctr, const uint8_t *in,
+                               uint8_t *out, size_t nbytes, hipStream_t stream) {
+    return launch_mode<kModeCtr>(k, ModeArgs{ctr}, in, out, nbytes, stream);
 }
 
 }  // namespace tdes

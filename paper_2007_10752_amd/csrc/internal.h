@@ -23,6 +23,12 @@ struct BitsliceKeys {
     uint32_t w[100];
 };
 
+// Per-launch arguments of the bitsliced kernel's modes (ECB ignores them).
+enum : int { kModeEcb = 0, kModeCtr = 1 };
+struct ModeArgs {
+    uint64_t ctr;  // CTR: counter of the buffer's first block (big-endian value)
+};
+
 // Kernel argument for the table kernel: per round, the key chunks XORed into
 // the right half where the S-box windows sit (see spbox.hip).
 struct SpboxKeys {
@@ -47,6 +53,9 @@ void spbox_keys(const RoundSequence &seq, SpboxKeys *out);
 // Launchers: enqueue on `stream`; return the HIP launch status.
 hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *out,
                            size_t nbytes, hipStream_t stream);
+// CTR mode: out = in XOR E(counter blocks ctr, ctr + 1, ...), k = encryption keys.
+hipError_t launch_bitslice_ctr(const BitsliceKeys &k, uint64_t ctr, const uint8_t *in,
+                               uint8_t *out, size_t nbytes, hipStream_t stream);
 size_t batch_workspace_bytes(size_t n_msgs);
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream);
 // The batched cipher alone, for a workspace whose first-slice table the

@@ -25,7 +25,8 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_probe_copy", "tdes_schedule_upload", "tdes_schedule_expand",
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
-           "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host")
+           "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host",
+           "tdes_ctr_crypt")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -78,6 +79,8 @@ def lib():
         L.tdes_batch_workspace_bytes.restype = sz
         L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp]
         L.tdes_batch_submit.restype = ctypes.c_int
+        L.tdes_ctr_crypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
+        L.tdes_ctr_crypt.restype = ctypes.c_int
         L.tdes_ecb_host.argtypes = [sched_p, ctypes.c_int, vp, vp, sz, vp, sz, sz]
         L.tdes_ecb_host.restype = ctypes.c_int
         L.tdes_kernel_key_bytes.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, sz]
@@ -154,6 +157,32 @@ def ecb(key, x, out=None, decrypt=False, kernel="auto", stream=None):
 
 def encrypt(key, x, out=None, kernel="auto", stream=None):
     return ecb(key, x, out, False, kernel, stream)
+
+
+def ctr_crypt_ptr(schedule, iv8, d_in, d_out, nbytes, stream=0):
+    iv = (ctypes.c_uint8 * 8).from_buffer_copy(bytes(bytearray(iv8)))
+    _check(lib().tdes_ctr_crypt(ctypes.byref(schedule), iv, ctypes.c_void_p(d_in),
+                                ctypes.c_void_p(d_out), ctypes.c_size_t(nbytes),
+                                ctypes.c_void_p(stream)))
+
+
+def ctr(key, iv8, x, out=None, stream=None):
+    """3DES-EDE in counter mode over a contiguous uint8 CUDA tensor: out =
+    x XOR E(counter blocks IV, IV + 1, ...), the 8-byte IV read as a
+    big-endian integer.  Its own inverse.  ``out`` may be ``x``."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.uint8 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous uint8 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    if not (out.is_cuda and out.dtype == torch.uint8 and out.is_contiguous()
+            and out.numel() == x.numel()):
+        raise ValueError("out must be a contiguous uint8 CUDA tensor shaped like x")
+    if len(bytes(bytearray(iv8))) != 8:
+        raise ValueError("iv must be 8 bytes")
+    ctr_crypt_ptr(_schedule(key), iv8, x.data_ptr(), out.data_ptr(), x.numel(),
+                  _stream_handle(stream))
+    return out
 
 
 HOST_MAX_SLOTS = 8

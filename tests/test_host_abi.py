@@ -107,6 +107,22 @@ def test_host_path_argument_errors():
     assert _host(nbytes=0, h_in=0, h_out=0, d_work=0) == 0  # empty: no-op
 
 
+def test_ctr_argument_errors():
+    s = T.key_schedule(bytes(24))
+    lib = T.lib()
+    iv = (ctypes.c_uint8 * 8)()
+
+    def call(nbytes=64, a=0x1000, b=0x100000, ivp=iv, sched=True):
+        return lib.tdes_ctr_crypt(ctypes.byref(s) if sched else None, ivp, ctypes.c_void_p(a),
+                                  ctypes.c_void_p(b), nbytes, None)
+    assert call(ivp=None) == -1
+    assert call(sched=False) == -1
+    assert call(nbytes=12) == -2
+    assert call(a=0x1004) == -3
+    assert call(b=0x1008) == -4
+    assert call(nbytes=0, a=0, b=0) == 0
+
+
 def _crypt_msg(n, a, b):
     _crypt(n, a, b)
     return T.lib().tdes_last_error()

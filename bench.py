@@ -3,9 +3,12 @@
 in HBM on one MI355X, through the library's C ABI.
 
 One step = key schedule of the 3-key bundle (host) + one fused 48-round
-encryption launch over the whole buffer.  W untimed warm-up steps, then K
-timed steps between device synchronisations; every launch is also bracketed
-by HIP events on the stream it runs on, which gives the kernel's own average
+encryption launch over the whole buffer.  The GPU's shader clock ramps up
+over the first ~60 ms of sustained load, so the step first repeats for
+--settle-seconds (the first 10 launches from idle are reported as
+settle.cold_first10_GBps); then W untimed warm-up steps, then K timed steps
+between device synchronisations.  Every launch is also bracketed by HIP
+events on the stream it runs on, which gives the kernel's own average
 duration for the roofline figure.  The oracle is timed on the host cores on
 a bounded sample of the same input (cpu_baseline).
 
@@ -35,8 +38,11 @@ def parse():
                     help="target wall time of the oracle sample (0 disables)")
     ap.add_argument("--batched", type=int, default=1,
                     help="also time the batched form (16,384 log-normal messages); 0 disables")
+    ap.add_argument("--settle-seconds", type=float, default=0.3,
+                    help="repeat the step this long before the warm-up steps: the shader clock "
+                         "ramps up over the first ~60 ms of sustained load (0 disables)")
     ap.add_argument("--modes", type=int, default=1,
-                    help="1: also time CTR mode on the same 1 GiB")
+                    help="1: also time CTR and CBC decryption on the same 1 GiB")
     ap.add_argument("--host", type=int, default=1,
                     help="1: also time the host-resident form (1 GiB pinned, PCIe included)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
@@ -288,10 +294,30 @@ def main():
         sched = tdes.key_schedule(key)
         tdes.ecb_crypt_ptr(sched, tdes.ENCRYPT, kernel, x.data_ptr(), out.data_ptr(), nbytes, sh)
 
+    # From idle: the first launches run while the clock ramps up (reported
+    # as cold_first10_GBps, not the value).
+    step()
+    torch.cuda.synchronize()
+    cold = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(10)]
+    for a, b in cold:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    cold_s = sum(a.elapsed_time(b) for a, b in cold) / len(cold) / 1e3
+    # Settle: the same step, repeated until the clock has ramped up.
+    t_settle = time.perf_counter()
+    n_settle = 0
+    while time.perf_counter() - t_settle < args.settle_seconds:
+        for _ in range(10):
+            step()
+        n_settle += 10
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    print("warmup done", file=sys.stderr, flush=True)
+    print("warmup done (%d settle steps)" % n_settle, file=sys.stderr, flush=True)
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -328,6 +354,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "settle": {"seconds": args.settle_seconds, "steps": n_settle,
+                   "cold_first10_GBps": round(nbytes / cold_s / 1e9, 3)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -358,6 +386,12 @@ def main():
         line["ctr"] = {"value": round(nbytes / t_ctr / 1e9, 3), "unit": "GB/s",
                        "ms": round(t_ctr * 1e3, 4),
                        "config": "same bytes and key in CTR mode, seeded 8-byte IV"}
+        t_cbc = time_launches(lambda: tdes.cbc_decrypt_ptr(sched, iv, x.data_ptr(),
+                                                           out.data_ptr(), nbytes, sh),
+                              max(3, args.steps), stream)
+        line["cbc_decrypt"] = {"value": round(nbytes / t_cbc / 1e9, 3), "unit": "GB/s",
+                               "ms": round(t_cbc * 1e3, 4),
+                               "config": "same bytes and key, CBC decryption, seeded 8-byte IV"}
         print("modes done", file=sys.stderr, flush=True)
     del x, out
     torch.cuda.empty_cache()

@@ -102,6 +102,19 @@ tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const v
 tdes_status tdes_ctr_crypt(const tdes_schedule *ks, const uint8_t iv[8], const void *d_in,
                            void *d_out, size_t nbytes, void *stream);
 
+/* 3DES-EDE CBC decryption over device memory (NIST SP 800-38A Sec. 6.2;
+ * the paper itself uses ECB only, Sec. V): output block i is
+ * D(input block i) XOR input block i - 1, with the IV (8 bytes, host
+ * memory) in place of input block -1.  D is the 3DES-EDE decryption of
+ * Sec. III-B with bundle ks.  Every block is independent of the other
+ * blocks' results, so it runs at full width; CBC encryption is serial
+ * within a message and is not offered.  The ciphertext blocks before each
+ * block are re-read from d_in, so d_in and d_out must not overlap at all
+ * (in place is TDES_ERR_OVERLAP).  Otherwise buffers, stream and errors as
+ * for tdes_ecb_decrypt, plus TDES_ERR_ARG for a NULL iv. */
+tdes_status tdes_cbc_decrypt(const tdes_schedule *ks, const uint8_t iv[8], const void *d_in,
+                             void *d_out, size_t nbytes, void *stream);
+
 /* ---- Batched form: many messages, each with its own key and direction --- */
 
 /* Bytes of device-resident key material per schedule (both directions). */

@@ -98,6 +98,25 @@ tdes_status tdes_ctr_crypt(const tdes_schedule *ks, const uint8_t iv[8], const v
     return TDES_OK;
 }
 
+tdes_status tdes_cbc_decrypt(const tdes_schedule *ks, const uint8_t iv[8], const void *d_in,
+                             void *d_out, size_t nbytes, void *stream) {
+    g_last_error.clear();
+    if (ks == nullptr || iv == nullptr) return fail(TDES_ERR_ARG, "NULL schedule or iv");
+    tdes_status st = check_buffers(d_in, d_out, nbytes);
+    if (st != TDES_OK || nbytes == 0) return st;
+    if (d_in == d_out)
+        return fail(TDES_ERR_OVERLAP, "CBC decryption re-reads the ciphertext: no in-place");
+    const uint32_t iv0 = iv[0] | iv[1] << 8 | iv[2] << 16 | (uint32_t)iv[3] << 24;
+    const uint32_t iv1 = iv[4] | iv[5] << 8 | iv[6] << 16 | (uint32_t)iv[7] << 24;
+    tdes::BitsliceKeys k;
+    tdes::bitslice_keys(*ks, TDES_DECRYPT, &k);
+    hipError_t e = tdes::launch_bitslice_cbc_dec(k, iv0, iv1, static_cast<const uint8_t *>(d_in),
+                                                 static_cast<uint8_t *>(d_out), nbytes,
+                                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
 tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
                              size_t nbytes, void *stream) {
     return tdes_ecb_crypt(ks, TDES_ENCRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);

@@ -25,7 +25,9 @@
 // Modes.  ECB processes the loaded blocks.  CTR (SP 800-38A) processes
 // counter blocks made in registers (the block at byte offset o holds
 // ctr + o / 8, big-endian) and XORs the data into the result on the way
-// out; nothing is loaded before the rounds.
+// out; nothing is loaded before the rounds.  CBC decryption decrypts the
+// loaded blocks, then XORs each with the ciphertext block before it (the
+// IV before the first), re-read after the rounds.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,7 +37,7 @@
 #include "internal.h"
 
 #ifndef TDES_CTR_MIN_WAVES
-#define TDES_CTR_MIN_WAVES 5  // CTR's budget (a few spills between the passes)
+#define TDES_CTR_MIN_WAVES 5  // CTR's and CBC's budget (a few spills between the passes)
 #endif
 #ifndef TDES_BS_MIN_WAVES
 #define TDES_BS_MIN_WAVES 4  // waves per SIMD the register budget must allow
@@ -59,6 +61,58 @@ __device__ __forceinline__ v4u load_piece_late(__amdgpu_buffer_rsrc_t src, uint3
     const v2u a = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off, k * 1024, 0);
     const v2u b = __builtin_amdgcn_raw_buffer_load_b64(src, lane_off + 8u, k * 1024, 0);
     return v4u{a[0], a[1], b[0], b[1]};
+}
+
+// CBC decryption output: XOR each decrypted block with the ciphertext block
+// before it.  Piece k's two previous blocks are the 16 bytes at 8 bytes
+// before the piece: prev resource offset vbase + k * 1024.  The first block
+// of the whole buffer takes the IV instead (the caller marks it with
+// first_iv and gives it the out-of-range offset voff0, read as 0).
+template <bool WHOLE>
+__device__ __forceinline__ void cbc_store_blocks(const uint32_t (&h0)[32], const uint32_t (&h1)[32],
+                                                 __amdgpu_buffer_rsrc_t prev,
+                                                 __amdgpu_buffer_rsrc_t dst, uint32_t lane_off,
+                                                 uint32_t voff0, uint32_t vbase, bool first_iv,
+                                                 uint32_t iv0, uint32_t iv1) {
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        __builtin_amdgcn_sched_barrier(0);
+        v4u pv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int k = 4 * g + j;
+            const uint32_t off = vbase + (uint32_t)(k * 1024);
+            if (k == 0) {
+                // two halves: block A's previous block (out of range where the
+                // IV stands in), block B's (block A itself)
+                const v2u a = __builtin_amdgcn_raw_buffer_load_b64(prev, voff0, 0, 0);
+                const v2u b = __builtin_amdgcn_raw_buffer_load_b64(prev, off + 8u, 0, 0);
+                pv[j] = v4u{a[0], a[1], b[0], b[1]};
+            } else if (WHOLE) {
+                pv[j] = __builtin_amdgcn_raw_buffer_load_b128(prev, off, 0, 0);
+            } else {
+                const v2u a = __builtin_amdgcn_raw_buffer_load_b64(prev, off, 0, 0);
+                const v2u b = __builtin_amdgcn_raw_buffer_load_b64(prev, off + 8u, 0, 0);
+                pv[j] = v4u{a[0], a[1], b[0], b[1]};
+            }
+        }
+        if (g == 0 && first_iv) {
+            pv[0][0] = iv0;
+            pv[0][1] = iv1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int k = 4 * g + j;
+            const v4u v = {h0[2 * k] ^ pv[j][0], h1[2 * k] ^ pv[j][1], h0[2 * k + 1] ^ pv[j][2],
+                           h1[2 * k + 1] ^ pv[j][3]};
+            if (WHOLE) {
+                __builtin_amdgcn_raw_buffer_store_b128(v, dst, lane_off, k * 1024, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b64(v2u{v[0], v[1]}, dst, lane_off, k * 1024, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(v2u{v[2], v[3]}, dst, lane_off + 8u, k * 1024, 0);
+            }
+        }
+    }
 }
 
 // CTR output: XOR the lane's 32 input blocks into its 32 keystream blocks
@@ -89,11 +143,11 @@ __device__ __forceinline__ void xor_store_blocks(const uint32_t (&h0)[32], const
     }
 }
 
-// ECB fits 5 waves per SIMD (96 registers) at the budget of 4; CTR needs the
-// 5-wave budget asked for explicitly.
+// ECB fits 5 waves per SIMD (96 registers) at the budget of 4; the other
+// modes need the 5-wave budget asked for explicitly.
 template <bool VEC16, int MODE>
 __global__ __launch_bounds__(kWave *kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(MODE == 0 ? TDES_BS_MIN_WAVES : TDES_CTR_MIN_WAVES, 8)))
+__attribute__((amdgpu_waves_per_eu(MODE == kModeEcb ? TDES_BS_MIN_WAVES : TDES_CTR_MIN_WAVES, 8)))
 void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, BitsliceKeys keys,
                           ModeArgs mode) {
     // Issue priority: a new wave's loads, mask expansion and transposes run
@@ -210,6 +264,27 @@ void tdes_bitslice_kernel(const uint8_t *in, uint8_t *out, size_t nbytes, Bitsli
             xor_store_blocks<false>(h0, h1, src, dst, lane_off);
         return;
     }
+    if (MODE == kModeCbcDec) {
+        // previous blocks: a resource from 8 bytes before the chunk (none
+        // before the first chunk, whose first block takes the IV), so every
+        // offset is non-negative
+        const uint32_t shift = base > 0 ? 8u : 0u;
+        const __amdgpu_buffer_rsrc_t prev = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(in + base - shift), 0, (int)(avail + shift), kBufferFlags);
+        const bool first_iv = base == 0 && lane_off == 0;
+        // lane_off + shift - 8 wraps for lane 0 of the first chunk; adding
+        // k * 1024 (k >= 1) brings it back to k * 1024 - 8, and piece 0 of
+        // that lane reads from an out-of-range offset instead
+        const uint32_t vbase = lane_off + shift - 8u;
+        const uint32_t voff0 = first_iv ? 0x40000000u : vbase;
+        if (whole)
+            cbc_store_blocks<true>(h0, h1, prev, dst, lane_off, voff0, vbase, first_iv, mode.iv0,
+                                   mode.iv1);
+        else
+            cbc_store_blocks<false>(h0, h1, prev, dst, lane_off, voff0, vbase, first_iv, mode.iv0,
+                                    mode.iv1);
+        return;
+    }
     if (whole) {
 #pragma unroll
         for (int k = 0; k < 16; k++) {
@@ -251,7 +326,13 @@ hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *ou
 
 hipError_t launch_bitslice_ctr(const BitsliceKeys &k, uint64_t ctr, const uint8_t *in,
                                uint8_t *out, size_t nbytes, hipStream_t stream) {
-    return launch_mode<kModeCtr>(k, ModeArgs{ctr}, in, out, nbytes, stream);
+    return launch_mode<kModeCtr>(k, ModeArgs{ctr, 0, 0}, in, out, nbytes, stream);
+}
+
+hipError_t launch_bitslice_cbc_dec(const BitsliceKeys &k, uint32_t iv0, uint32_t iv1,
+                                   const uint8_t *in, uint8_t *out, size_t nbytes,
+                                   hipStream_t stream) {
+    return launch_mode<kModeCbcDec>(k, ModeArgs{0, iv0, iv1}, in, out, nbytes, stream);
 }
 
 }  // namespace tdes

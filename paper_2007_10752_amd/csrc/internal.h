@@ -24,9 +24,10 @@ struct BitsliceKeys {
 };
 
 // Per-launch arguments of the bitsliced kernel's modes (ECB ignores them).
-enum : int { kModeEcb = 0, kModeCtr = 1 };
+enum : int { kModeEcb = 0, kModeCtr = 1, kModeCbcDec = 2 };
 struct ModeArgs {
-    uint64_t ctr;  // CTR: counter of the buffer's first block (big-endian value)
+    uint64_t ctr;       // CTR: counter of the buffer's first block (big-endian value)
+    uint32_t iv0, iv1;  // CBC: the IV's bytes 0-3 and 4-7, little-endian words
 };
 
 // Kernel argument for the table kernel: per round, the key chunks XORed into
@@ -56,6 +57,11 @@ hipError_t launch_bitslice(const BitsliceKeys &k, const uint8_t *in, uint8_t *ou
 // CTR mode: out = in XOR E(counter blocks ctr, ctr + 1, ...), k = encryption keys.
 hipError_t launch_bitslice_ctr(const BitsliceKeys &k, uint64_t ctr, const uint8_t *in,
                                uint8_t *out, size_t nbytes, hipStream_t stream);
+// CBC decryption: out block i = D(in block i) XOR in block i - 1 (the IV for
+// i = 0), k = decryption keys; in and out must not overlap.
+hipError_t launch_bitslice_cbc_dec(const BitsliceKeys &k, uint32_t iv0, uint32_t iv1,
+                                   const uint8_t *in, uint8_t *out, size_t nbytes,
+                                   hipStream_t stream);
 size_t batch_workspace_bytes(size_t n_msgs);
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream);
 // The batched cipher alone, for a workspace whose first-slice table the

@@ -26,7 +26,7 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
            "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host",
-           "tdes_ctr_crypt")
+           "tdes_ctr_crypt", "tdes_cbc_decrypt")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -81,6 +81,8 @@ def lib():
         L.tdes_batch_submit.restype = ctypes.c_int
         L.tdes_ctr_crypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
         L.tdes_ctr_crypt.restype = ctypes.c_int
+        L.tdes_cbc_decrypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
+        L.tdes_cbc_decrypt.restype = ctypes.c_int
         L.tdes_ecb_host.argtypes = [sched_p, ctypes.c_int, vp, vp, sz, vp, sz, sz]
         L.tdes_ecb_host.restype = ctypes.c_int
         L.tdes_kernel_key_bytes.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, sz]
@@ -182,6 +184,32 @@ def ctr(key, iv8, x, out=None, stream=None):
         raise ValueError("iv must be 8 bytes")
     ctr_crypt_ptr(_schedule(key), iv8, x.data_ptr(), out.data_ptr(), x.numel(),
                   _stream_handle(stream))
+    return out
+
+
+def cbc_decrypt_ptr(schedule, iv8, d_in, d_out, nbytes, stream=0):
+    iv = (ctypes.c_uint8 * 8).from_buffer_copy(bytes(bytearray(iv8)))
+    _check(lib().tdes_cbc_decrypt(ctypes.byref(schedule), iv, ctypes.c_void_p(d_in),
+                                  ctypes.c_void_p(d_out), ctypes.c_size_t(nbytes),
+                                  ctypes.c_void_p(stream)))
+
+
+def cbc_decrypt(key, iv8, x, out=None, stream=None):
+    """3DES-EDE CBC decryption of a contiguous uint8 CUDA tensor: out block i
+    = D(x block i) XOR x block i - 1 (the 8-byte IV before the first).
+    ``out`` must not overlap ``x``."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.uint8 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous uint8 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    if not (out.is_cuda and out.dtype == torch.uint8 and out.is_contiguous()
+            and out.numel() == x.numel()):
+        raise ValueError("out must be a contiguous uint8 CUDA tensor shaped like x")
+    if len(bytes(bytearray(iv8))) != 8:
+        raise ValueError("iv must be 8 bytes")
+    cbc_decrypt_ptr(_schedule(key), iv8, x.data_ptr(), out.data_ptr(), x.numel(),
+                    _stream_handle(stream))
     return out
 
 

@@ -1,5 +1,6 @@
-"""GPU parity of the other modes over the bitsliced kernel: CTR
-(tdes_ctr_crypt), bit for bit against the oracle's CTR.
+"""GPU parity of the other modes over the bitsliced kernel, bit for bit
+against the oracle: CTR (tdes_ctr_crypt) and CBC decryption
+(tdes_cbc_decrypt).
 
 The cases are:
 
@@ -9,7 +10,13 @@ The cases are:
 * 8-byte-aligned and in-place buffers;
 * the 64 MiB case in full;
 * the 1 GiB case on seeded runs of blocks, checked one run at a time (the
-  oracle's CTR from the IV advanced to the run's first block)."""
+  oracle's CTR from the IV advanced to the run's first block).
+
+CBC decryption: the same ragged sizes (the first block of every wave chunk
+takes its previous block from the chunk before, the buffer's first block
+the IV), 8-byte-aligned buffers, the 64 MiB case in full, and the 1 GiB
+case on seeded runs (the oracle's CBC decryption of a run, with the
+ciphertext block before the run as its IV)."""
 import sys
 
 import numpy as np
@@ -112,4 +119,73 @@ def test_ctr_1gib_runs(torch_dev):
     for s0 in starts.tolist():
         a, b = 8 * s0, 8 * (s0 + run)
         want = oracle.tdes_ctr(key, _iv(iv_v + s0), x[a:b].cpu().numpy())
+        assert np.array_equal(out[a:b].cpu().numpy(), want), s0
+
+
+def _cbc_gpu(torch, key, iv, data, offset=0):
+    buf = torch.zeros(data.size + offset, dtype=torch.uint8, device="cuda")
+    x = buf[offset:]
+    x.copy_(torch.from_numpy(data))
+    out = T.cbc_decrypt(key, iv, x)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("nblocks", RAGGED)
+def test_cbc_decrypt_ragged_sizes(torch_dev, nblocks):
+    g = W.rng(W.SEED_BASE + 0x740 + nblocks)
+    key = W.key_bundle(g)
+    iv = W.uniform_bytes(g, 8)
+    data = W.uniform_bytes(g, 8 * nblocks)
+    _say("cbc ragged", nblocks)
+    got = _cbc_gpu(torch_dev, key, iv, data)
+    assert np.array_equal(got, oracle.tdes_cbc_decrypt(key, iv, data))
+
+
+def test_cbc_decrypt_round_trip_and_unaligned(torch_dev):
+    g = W.rng(W.SEED_BASE + 0x750)
+    key = W.key_bundle(g, two_key=True)
+    iv = W.uniform_bytes(g, 8)
+    plain = W.uniform_bytes(g, 8 * 3000)
+    ct = oracle.tdes_cbc_encrypt(key, iv, plain)
+    _say("cbc round trip")
+    assert np.array_equal(_cbc_gpu(torch_dev, key, iv, ct), plain)
+    assert np.array_equal(_cbc_gpu(torch_dev, key, iv, ct, offset=8), plain)
+
+
+def test_cbc_decrypt_refuses_in_place(torch_dev):
+    torch = torch_dev
+    x = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(T.TdesError) as e:
+        T.cbc_decrypt(bytes(24), bytes(8), x, x)
+    assert e.value.status == -4
+
+
+def test_cbc_decrypt_64mib_full(torch_dev):
+    g = W.rng(W.SEED_BASE + 1)
+    data = W.uniform_bytes(g, 8 * 8388608)
+    key = W.key_bundle(W.rng(W.SEED_BASE + 1 + W.KEY_SEED_OFFSET))
+    iv = W.uniform_bytes(W.rng(W.SEED_BASE + 0x760), 8)
+    _say("cbc 64MiB")
+    got = _cbc_gpu(torch_dev, key, iv, data)
+    assert np.array_equal(got, oracle.tdes_cbc_decrypt(key, iv, data))
+
+
+def test_cbc_decrypt_1gib_runs(torch_dev):
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 2)
+    key = W.key_bundle(W.rng(W.SEED_BASE + 2 + W.KEY_SEED_OFFSET))
+    iv = W.uniform_bytes(g, 8)
+    _say("cbc 1GiB")
+    x = torch.from_numpy(W.uniform_bytes(g, 1 << 30)).cuda()
+    out = T.cbc_decrypt(key, iv, x)
+    torch.cuda.synchronize()
+    nblk = (1 << 30) // 8
+    run = 512
+    starts = np.sort(W.rng(W.SEED_BASE + 0x770).choice(nblk // run, 64, replace=False)) * run
+    starts = np.concatenate([[0], starts, [nblk - run]])
+    for s0 in starts.tolist():
+        a, b = 8 * s0, 8 * (s0 + run)
+        run_iv = iv if s0 == 0 else x[a - 8:a].cpu().numpy()
+        want = oracle.tdes_cbc_decrypt(key, run_iv, x[a:b].cpu().numpy())
         assert np.array_equal(out[a:b].cpu().numpy(), want), s0

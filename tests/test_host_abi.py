@@ -123,6 +123,23 @@ def test_ctr_argument_errors():
     assert call(nbytes=0, a=0, b=0) == 0
 
 
+def test_cbc_argument_errors():
+    s = T.key_schedule(bytes(24))
+    lib = T.lib()
+    iv = (ctypes.c_uint8 * 8)()
+
+    def call(nbytes=64, a=0x1000, b=0x100000, ivp=iv, sched=True):
+        return lib.tdes_cbc_decrypt(ctypes.byref(s) if sched else None, ivp, ctypes.c_void_p(a),
+                                    ctypes.c_void_p(b), nbytes, None)
+    assert call(ivp=None) == -1
+    assert call(sched=False) == -1
+    assert call(nbytes=12) == -2
+    assert call(a=0x1004) == -3
+    assert call(b=0x1008) == -4
+    assert call(b=0x1000) == -4  # in place: the ciphertext is re-read
+    assert call(nbytes=0, a=0, b=0) == 0
+
+
 def _crypt_msg(n, a, b):
     _crypt(n, a, b)
     return T.lib().tdes_last_error()

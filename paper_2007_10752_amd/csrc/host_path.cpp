@@ -84,14 +84,23 @@ hipError_t run_host_pipeline(const BitsliceKeys &k, const uint8_t *h_in, uint8_t
 // Device address of the host range [h, h + n): h must be pinned host memory
 // mapped into the device's address space, and the whole range must lie in
 // the allocation that holds h (a kernel must never touch an unmapped page).
+// A refused range is an argument error, not a device failure: the HIP
+// runtime's last-error state is cleared, or the caller's next HIP call (a
+// torch launch, say) would report it as its own.
 hipError_t mapped_range(const void *h, size_t n, uint8_t **d) {
     void *a = nullptr;
     hipError_t e = hipHostGetDevicePointer(&a, const_cast<void *>(h), 0);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
     hipDeviceptr_t base = nullptr;
     size_t size = 0;
     e = hipMemGetAddressRange(&base, &size, a);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
     const uintptr_t lo = (uintptr_t)base, p = (uintptr_t)a;
     if (p < lo || p - lo > size || n > size - (p - lo)) return hipErrorInvalidValue;
     *d = static_cast<uint8_t *>(a);

@@ -144,3 +144,5 @@ def test_direct_refuses_unmapped_ranges(torch_dev):
                        None, 0, 0)
     assert e.value.status == -1
     assert np.array_equal(h.numpy(), data)  # untouched
+    # the refusals leave no HIP error behind for the next call to report
+    assert torch.zeros(8, device="cuda").sum().item() == 0

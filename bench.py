@@ -42,7 +42,7 @@ def parse():
                     help="repeat the step this long before the warm-up steps: the shader clock "
                          "ramps up over the first ~60 ms of sustained load (0 disables)")
     ap.add_argument("--modes", type=int, default=1,
-                    help="1: also time CTR and CBC decryption on the same 1 GiB")
+                    help="1: also time CTR, CBC decryption and the paper's design on the same 1 GiB")
     ap.add_argument("--host", type=int, default=1,
                     help="1: also time the host-resident form (1 GiB pinned, PCIe included)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
@@ -392,6 +392,13 @@ def main():
         line["cbc_decrypt"] = {"value": round(nbytes / t_cbc / 1e9, 3), "unit": "GB/s",
                                "ms": round(t_cbc * 1e3, 4),
                                "config": "same bytes and key, CBC decryption, seeded 8-byte IV"}
+        t_paper = time_launches(lambda: tdes.paper_design_ptr(sched, tdes.ENCRYPT, x.data_ptr(),
+                                                               out.data_ptr(), nbytes, sh),
+                                3, stream)
+        line["paper_design"] = {"value": round(nbytes / t_paper / 1e9, 3), "unit": "GB/s",
+                                "ms": round(t_paper * 1e3, 3),
+                                "config": "same bytes and key, ECB encrypt with the paper's "
+                                          "one-thread-per-bit design (three launches)"}
         print("modes done", file=sys.stderr, flush=True)
     del x, out
     torch.cuda.empty_cache()

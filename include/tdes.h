@@ -115,6 +115,15 @@ tdes_status tdes_ctr_crypt(const tdes_schedule *ks, const uint8_t iv[8], const v
 tdes_status tdes_cbc_decrypt(const tdes_schedule *ks, const uint8_t iv[8], const void *d_in,
                              void *d_out, size_t nbytes, void *stream);
 
+/* The paper's own GPU design (Sec. IV-B, IV-C), for comparison only: one
+ * 64-thread workgroup per block, one thread per bit, bits one per byte in
+ * LDS, tables read at run time, a barrier between steps, and three launches
+ * (one per DES pass; decryption passes take their round keys reversed, as
+ * the paper does on the host).  Same result as tdes_ecb_crypt; far slower.
+ * Buffers, stream and errors as for tdes_ecb_crypt (no kernel argument). */
+tdes_status tdes_ecb_paper_design(const tdes_schedule *ks, int dir, const void *d_in, void *d_out,
+                                  size_t nbytes, void *stream);
+
 /* ---- Batched form: many messages, each with its own key and direction --- */
 
 /* Bytes of device-resident key material per schedule (both directions). */

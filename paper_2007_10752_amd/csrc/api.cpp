@@ -117,6 +117,34 @@ tdes_status tdes_cbc_decrypt(const tdes_schedule *ks, const uint8_t iv[8], const
     return TDES_OK;
 }
 
+tdes_status tdes_ecb_paper_design(const tdes_schedule *ks, int dir, const void *d_in, void *d_out,
+                                  size_t nbytes, void *stream) {
+    g_last_error.clear();
+    if (ks == nullptr) return fail(TDES_ERR_ARG, "NULL schedule");
+    if (dir != TDES_ENCRYPT && dir != TDES_DECRYPT) return fail(TDES_ERR_ARG, "bad direction %d", dir);
+    tdes_status st = check_buffers(d_in, d_out, nbytes);
+    if (st != TDES_OK || nbytes == 0) return st;
+    // The three passes in order, as (base key, decrypt?): E_K1, D_K2, E_K3;
+    // decryption D_K3, E_K2, D_K1 (Sec. III-B).  A decrypting pass takes the
+    // round keys in reverse (Sec. IV-B: reversed on the host).
+    const int key_of[2][3] = {{0, 1, 2}, {2, 1, 0}};
+    const bool dec_of[2][3] = {{false, true, false}, {true, false, true}};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int pass = 0; pass < 3; pass++) {
+        tdes::ReplicaKeyBits kb;
+        const uint64_t *rk = ks->k[key_of[dir][pass]];
+        for (int i = 0; i < 16; i++) {
+            const uint64_t key = rk[dec_of[dir][pass] ? 15 - i : i];
+            for (int j = 0; j < 48; j++) kb.k[48 * i + j] = (uint8_t)((key >> (47 - j)) & 1);
+        }
+        hipError_t e = tdes::launch_replica_pass(kb, pass == 0 ? static_cast<const uint8_t *>(d_in)
+                                                               : static_cast<const uint8_t *>(d_out),
+                                                 static_cast<uint8_t *>(d_out), nbytes, s);
+        if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    return TDES_OK;
+}
+
 tdes_status tdes_ecb_encrypt(const tdes_schedule *ks, const void *d_in, void *d_out,
                              size_t nbytes, void *stream) {
     return tdes_ecb_crypt(ks, TDES_ENCRYPT, TDES_KERNEL_AUTO, d_in, d_out, nbytes, stream);

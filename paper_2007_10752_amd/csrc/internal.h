@@ -30,6 +30,13 @@ struct ModeArgs {
     uint32_t iv0, iv1;  // CBC: the IV's bytes 0-3 and 4-7, little-endian words
 };
 
+// Kernel argument for the one-thread-per-bit comparison kernel: the 16
+// round keys of one DES pass in application order, one byte (0 or 1) per
+// key bit, round i at 48 i (bit 1 first).
+struct ReplicaKeyBits {
+    uint8_t k[16 * 48];
+};
+
 // Kernel argument for the table kernel: per round, the key chunks XORed into
 // the right half where the S-box windows sit (see spbox.hip).
 struct SpboxKeys {
@@ -75,6 +82,10 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                         hipStream_t stream);
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
+
+// One DES pass of the one-thread-per-bit comparison kernel (in may equal out).
+hipError_t launch_replica_pass(const ReplicaKeyBits &k, const uint8_t *in, uint8_t *out,
+                               size_t nbytes, hipStream_t stream);
 
 // Host-resident pipeline behind tdes_ecb_host (arguments already checked):
 // chunks of `chunk` bytes through n_slots device slots at d_work; returns

@@ -26,7 +26,7 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
            "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host",
-           "tdes_ctr_crypt", "tdes_cbc_decrypt")
+           "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_paper_design")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -83,6 +83,8 @@ def lib():
         L.tdes_ctr_crypt.restype = ctypes.c_int
         L.tdes_cbc_decrypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
         L.tdes_cbc_decrypt.restype = ctypes.c_int
+        L.tdes_ecb_paper_design.argtypes = [sched_p, ctypes.c_int, vp, vp, sz, vp]
+        L.tdes_ecb_paper_design.restype = ctypes.c_int
         L.tdes_ecb_host.argtypes = [sched_p, ctypes.c_int, vp, vp, sz, vp, sz, sz]
         L.tdes_ecb_host.restype = ctypes.c_int
         L.tdes_kernel_key_bytes.argtypes = [sched_p, ctypes.c_int, ctypes.c_int, vp, sz]
@@ -211,6 +213,13 @@ def cbc_decrypt(key, iv8, x, out=None, stream=None):
     cbc_decrypt_ptr(_schedule(key), iv8, x.data_ptr(), out.data_ptr(), x.numel(),
                     _stream_handle(stream))
     return out
+
+
+def paper_design_ptr(schedule, direction, d_in, d_out, nbytes, stream=0):
+    """The paper's one-thread-per-bit design (comparison only)."""
+    _check(lib().tdes_ecb_paper_design(ctypes.byref(schedule), direction, ctypes.c_void_p(d_in),
+                                       ctypes.c_void_p(d_out), ctypes.c_size_t(nbytes),
+                                       ctypes.c_void_p(stream)))
 
 
 HOST_MAX_SLOTS = 8

@@ -203,5 +203,6 @@ def generated_headers_match():
     """True if the committed headers equal what the emitter writes now."""
     nets = load_networks()
     want = {"des_tables_gen.h": emit.emit_tables(), "bitslice_gen.h": emit.emit_bitslice(nets),
-            "bitslice_keys_gen.h": emit.emit_bitslice_keys(), "spbox_gen.h": emit.emit_spbox()}
+            "bitslice_keys_gen.h": emit.emit_bitslice_keys(), "spbox_gen.h": emit.emit_spbox(),
+            "replica_tables_gen.h": emit.emit_replica_tables()}
     return {name: _header(name) == text for name, text in want.items()}

@@ -264,6 +264,36 @@ def test_offsets_beyond_4gib(torch_dev, kernel):
     assert same
 
 
+@pytest.mark.parametrize("nblocks", [1, 3, 4096, 12345])
+@pytest.mark.parametrize("two_key", [False, True])
+def test_paper_design_matches_oracle(torch_dev, nblocks, two_key):
+    # The paper's one-thread-per-bit design (three launches), both directions.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x80 + nblocks + two_key)
+    key = W.key_bundle(g, two_key=two_key)
+    data = W.uniform_bytes(g, 8 * nblocks)
+    _say("paper design", nblocks, "two_key", two_key)
+    x = torch.from_numpy(data).cuda()
+    for dec in (False, True):
+        out = torch.empty_like(x)
+        T.paper_design_ptr(T.key_schedule(key), T.DECRYPT if dec else T.ENCRYPT, x.data_ptr(),
+                           out.data_ptr(), x.numel(), int(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.tdes_ecb(key, data, dec)), dec
+
+
+def test_paper_design_64mib_equals_bitsliced(torch_dev):
+    torch = torch_dev
+    key, data, want = _c2_case(False)
+    _say("paper design 64MiB")
+    x = torch.from_numpy(data).cuda()
+    out = torch.empty_like(x)
+    T.paper_design_ptr(T.key_schedule(key), T.ENCRYPT, x.data_ptr(), out.data_ptr(), x.numel(),
+                       int(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 def test_valu_probes_run(torch_dev):
     # The issue-rate probes the roofline discussion rests on: every opcode
     # launches and returns a positive rate.

@@ -120,8 +120,14 @@ def batched_section(steps):
             tdes.ecb_crypt_ptr(scheds[i], dirs[i], 1, xb + offs[i], ob + offs[i], lens[i], sh)
 
     t_loop = time_launches(per_message, 1, stream)
+    # the same batch captured once in a HIP graph and replayed
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.submit(x, out, stream=torch.cuda.current_stream())
+    t_graph = time_launches(graph.replay, max(3, steps), stream)
     return {"value": round(total / t_batch / 1e9, 3), "unit": "GB/s",
             "ms": round(t_batch * 1e3, 4), "messages": len(lens), "bytes": total,
+            "graph_replay_GBps": round(total / t_graph / 1e9, 3),
             "plain_same_bytes_GBps": round(total / t_plain / 1e9, 3),
             "per_message_launches_GBps": round(total / t_loop / 1e9, 3),
             "config": "16384 msgs, lognormal median 4 KiB sigma 1, clip 8 B..1 MiB, "

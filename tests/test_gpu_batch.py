@@ -208,3 +208,43 @@ def test_device_key_expansion_matches_host(torch_dev):
     T.schedule_expand(dk.data_ptr(), n, b.data_ptr(), int(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_batch_replays_in_a_captured_graph(torch_dev):
+    # The batched call only enqueues kernels on the caller's stream (no
+    # memset, no allocation, no synchronisation), so it can be captured in a
+    # HIP graph.  Each replay, with eager work and a new input in between,
+    # must equal the eager result on the same input.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x308)
+    n = 300
+    lengths = (g.integers(0, 120, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    total = int(lengths.sum())
+    offs = np.zeros(n, dtype=np.int64)
+    offs[1:] = np.cumsum(lengths)[:-1]
+    x = torch.from_numpy(W.uniform_bytes(g, total)).cuda()
+    out = torch.empty_like(x)
+    b = T.Batch(keys, offs, offs, lengths, dirs)
+    b.submit(x, out)  # eager first: one-time set-up happens outside the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.submit(x, out, stream=torch.cuda.current_stream())
+    _say("batch graph replays")
+    for r in range(3):
+        x.copy_(torch.from_numpy(W.uniform_bytes(W.rng(W.SEED_BASE + 0x309 + r), total)))
+        out.fill_(r)
+        want = torch.full_like(x, 0xA5)
+        b.submit(x, want)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), r
+        assert b.skipped() == 0
+    got = out.cpu().numpy()
+    data = x.cpu().numpy()
+    for i in range(0, n, 37):
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i

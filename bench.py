@@ -106,6 +106,7 @@ def batched_section(steps):
     out = torch.empty_like(x)
     stream = torch.cuda.current_stream()
     b = tdes.Batch(lay["keys"], lay["offsets"], lay["offsets"], lay["lengths"], lay["dirs"])
+    mult = b.autotune(x, out, reps=3)
     t_batch = time_launches(lambda: b.submit(x, out), max(3, steps), stream)
     sched = tdes.key_schedule(lay["keys"][0])
     sh = int(stream.cuda_stream)
@@ -128,6 +129,7 @@ def batched_section(steps):
     return {"value": round(total / t_batch / 1e9, 3), "unit": "GB/s",
             "ms": round(t_batch * 1e3, 4), "messages": len(lens), "bytes": total,
             "graph_replay_GBps": round(total / t_graph / 1e9, 3),
+            "autotuned_grid_multiplier": mult,
             "plain_same_bytes_GBps": round(total / t_plain / 1e9, 3),
             "per_message_launches_GBps": round(total / t_loop / 1e9, 3),
             "config": "16384 msgs, lognormal median 4 KiB sigma 1, clip 8 B..1 MiB, "

@@ -232,6 +232,20 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
 tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, void *h_out,
                           size_t nbytes, void *d_work, size_t work_bytes, size_t chunk_bytes);
 
+/* Autotuner for the batched form: runs this batch (arguments and checks as
+ * for tdes_batch_submit) at grids of 1, 2, 3 and 4 times the workgroups
+ * that fit on the GPU at once, reps (>= 1) times each after one warm run,
+ * timed with HIP events on `stream`.  The fastest grid is kept for every
+ * later tdes_batch_submit on the current device (and the request server's
+ * batches); its multiplier is written to *grid_multiplier.  Synchronous.
+ * The output is written several times, each time with the same result.
+ * Errors: those of tdes_batch_submit, and TDES_ERR_ARG for reps < 1 or a
+ * NULL grid_multiplier. */
+tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                                size_t n_schedules, const void *d_in_base, void *d_out_base,
+                                void *d_workspace, size_t workspace_bytes, void *stream, int reps,
+                                int *grid_multiplier);
+
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
  * TDES_KERNEL_SPBOX; AUTO means the kernel AUTO selects) would receive for
  * schedule ks and direction dir, copied to host memory `out` (cap bytes).

@@ -36,6 +36,24 @@ tdes_status check_buffers(const void *in, const void *out, size_t nbytes) {
     return TDES_OK;
 }
 
+// Checks shared by the batched calls (n_msgs > 0).
+tdes_status tdes_batch_submit_checks(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                                     size_t n_schedules, const void *d_in_base,
+                                     const void *d_out_base, const void *d_workspace,
+                                     size_t workspace_bytes) {
+    if (d_msgs == nullptr || d_schedules == nullptr || d_in_base == nullptr ||
+        d_out_base == nullptr || d_workspace == nullptr)
+        return fail(TDES_ERR_ARG, "NULL pointer");
+    if (n_schedules == 0) return fail(TDES_ERR_ARG, "no schedules");
+    if (workspace_bytes < tdes::batch_workspace_bytes(n_msgs))
+        return fail(TDES_ERR_ARG, "workspace too small (%zu < %zu bytes)", workspace_bytes,
+                    tdes::batch_workspace_bytes(n_msgs));
+    if (((uintptr_t)d_msgs | (uintptr_t)d_in_base | (uintptr_t)d_out_base |
+         (uintptr_t)d_workspace) % 8 != 0 || (uintptr_t)d_schedules % 16 != 0)
+        return fail(TDES_ERR_ALIGN, "misaligned pointer");
+    return TDES_OK;
+}
+
 }  // namespace
 
 tdes_status tdes::set_last_error(tdes_status st, const char *msg) {
@@ -226,22 +244,36 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
                               void *d_workspace, size_t workspace_bytes, void *stream) {
     g_last_error.clear();
     if (n_msgs == 0) return TDES_OK;
-    if (d_msgs == nullptr || d_schedules == nullptr || d_in_base == nullptr ||
-        d_out_base == nullptr || d_workspace == nullptr)
-        return fail(TDES_ERR_ARG, "NULL pointer");
-    if (n_schedules == 0) return fail(TDES_ERR_ARG, "no schedules");
-    if (workspace_bytes < tdes::batch_workspace_bytes(n_msgs))
-        return fail(TDES_ERR_ARG, "workspace too small (%zu < %zu bytes)", workspace_bytes,
-                    tdes::batch_workspace_bytes(n_msgs));
-    if (((uintptr_t)d_msgs | (uintptr_t)d_in_base | (uintptr_t)d_out_base |
-         (uintptr_t)d_workspace) % 8 != 0 || (uintptr_t)d_schedules % 16 != 0)
-        return fail(TDES_ERR_ALIGN, "misaligned pointer");
+    tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
+                                              d_out_base, d_workspace, workspace_bytes);
+    if (st != TDES_OK) return st;
     hipError_t e = tdes::launch_batch(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
                                       n_schedules, static_cast<const uint8_t *>(d_in_base),
                                       static_cast<uint8_t *>(d_out_base),
                                       static_cast<uint64_t *>(d_workspace),
                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
+tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                                size_t n_schedules, const void *d_in_base, void *d_out_base,
+                                void *d_workspace, size_t workspace_bytes, void *stream, int reps,
+                                int *grid_multiplier) {
+    g_last_error.clear();
+    if (reps < 1 || grid_multiplier == nullptr)
+        return fail(TDES_ERR_ARG, "reps must be >= 1 and grid_multiplier non-NULL");
+    if (n_msgs == 0) return fail(TDES_ERR_ARG, "nothing to tune on: no messages");
+    // same checks as tdes_batch_submit
+    tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
+                                              d_out_base, d_workspace, workspace_bytes);
+    if (st != TDES_OK) return st;
+    hipError_t e = tdes::batch_autotune(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
+                                        n_schedules, static_cast<const uint8_t *>(d_in_base),
+                                        static_cast<uint8_t *>(d_out_base),
+                                        static_cast<uint64_t *>(d_workspace),
+                                        static_cast<hipStream_t>(stream), reps, grid_multiplier);
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "autotune failed: %s", hipGetErrorString(e));
     return TDES_OK;
 }
 

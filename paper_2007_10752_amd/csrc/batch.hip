@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "bitslice_core.h"
 #include "internal.h"
 
@@ -261,17 +263,36 @@ __global__ __launch_bounds__(256) void expand_kernel(const uint8_t *keys24, size
 // wherever one finishes, so the last groups of a batch are spread over the
 // whole GPU instead of being left to the persistent waves' final pass (a
 // wave with no group left exits at once).
-int batch_grid_blocks() {
-    static int n = 0;
-    if (n == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+//
+// The multiplier is TDES_BATCH_GRID_MULT unless tdes_batch_autotune has
+// measured a better one for the current device.
+constexpr int kMaxDevices = 64;
+constexpr int kMaxGridMult = 4;
+std::atomic<int> g_tuned_mult[kMaxDevices];  // 0: not tuned
+
+int current_device() {
+    int dev = 0;
+    return hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices ? dev : 0;
+}
+
+int resident_blocks() {
+    static std::atomic<int> n{0};
+    int v = n.load();
+    if (v == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, current_device()) !=
+                hipSuccess ||
             cus <= 0)
             cus = 256;
-        n = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock * TDES_BATCH_GRID_MULT;  // 4 SIMDs/CU
+        v = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock;  // 4 SIMDs per CU
+        n.store(v);
     }
-    return n;
+    return v;
+}
+
+int batch_grid_blocks() {
+    const int m = g_tuned_mult[current_device()].load();
+    return resident_blocks() * (m > 0 ? m : TDES_BATCH_GRID_MULT);
 }
 
 }  // namespace
@@ -290,6 +311,37 @@ hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint
     hipLaunchKernelGGL(batch_bitslice_kernel, dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
                        msgs, n_msgs, schedules, n_schedules, in, out, ws);
     return hipGetLastError();
+}
+
+hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
+                          size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
+                          hipStream_t stream, int reps, int *mult_out) {
+    const int dev = current_device();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    float best_ms = 0;
+    int best = TDES_BATCH_GRID_MULT;
+    for (int m = 1; m <= kMaxGridMult && e == hipSuccess; m++) {
+        g_tuned_mult[dev].store(m);
+        e = launch_batch(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);  // warm
+        if (e == hipSuccess) e = hipEventRecord(a, stream);
+        for (int r = 0; r < reps && e == hipSuccess; r++)
+            e = launch_batch(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);
+        if (e == hipSuccess) e = hipEventRecord(b, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (m == 1 || ms < best_ms)) {
+            best_ms = ms;
+            best = m;
+        }
+    }
+    g_tuned_mult[dev].store(e == hipSuccess ? best : 0);
+    if (a != nullptr) (void)hipEventDestroy(a);
+    if (b != nullptr) (void)hipEventDestroy(b);
+    if (e == hipSuccess) *mult_out = best;
+    return e;
 }
 
 size_t batch_workspace_bytes(size_t n_msgs) { return (kWsHeader + n_msgs + 1) * sizeof(uint64_t); }

@@ -80,6 +80,13 @@ hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint
 hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                         size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
                         hipStream_t stream);
+// Times the batch (scan + cipher, `reps` runs after one warm run) at grids
+// of 1..4 times the resident workgroups on `stream`, keeps the fastest for
+// later batched launches on the current device and returns its multiplier.
+// Synchronous.
+hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
+                          size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
+                          hipStream_t stream, int reps, int *mult_out);
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 

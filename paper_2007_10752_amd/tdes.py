@@ -26,7 +26,8 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
            "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host",
-           "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_paper_design")
+           "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_paper_design",
+           "tdes_batch_autotune")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -79,6 +80,9 @@ def lib():
         L.tdes_batch_workspace_bytes.restype = sz
         L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp]
         L.tdes_batch_submit.restype = ctypes.c_int
+        L.tdes_batch_autotune.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]
+        L.tdes_batch_autotune.restype = ctypes.c_int
         L.tdes_ctr_crypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
         L.tdes_ctr_crypt.restype = ctypes.c_int
         L.tdes_cbc_decrypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
@@ -376,6 +380,19 @@ class Batch:
                          x.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
                          _stream_handle(stream) if stream is not None else self.stream)
         return out
+
+    def autotune(self, x, out, reps=3, stream=None):
+        """Time this batch at grids of 1..4 times the resident workgroups and
+        keep the fastest for later batched launches on this device; returns
+        the chosen multiplier (synchronous)."""
+        m = ctypes.c_int(0)
+        _check(lib().tdes_batch_autotune(
+            ctypes.c_void_p(self.msgs.data_ptr()), self.n_msgs, ctypes.c_void_p(self.sched.data_ptr()),
+            self.n_sched, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+            ctypes.c_void_p(_stream_handle(stream) if stream is not None else self.stream),
+            int(reps), ctypes.byref(m)))
+        return m.value
 
     def skipped(self):
         """Messages the last submit skipped as invalid (synchronises)."""

@@ -248,3 +248,31 @@ def test_batch_replays_in_a_captured_graph(torch_dev):
     for i in range(0, n, 37):
         seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
         assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
+def test_batch_autotune_keeps_results(torch_dev):
+    # The autotuner runs the batch at several grids; every run, and every
+    # later submit at the chosen grid, gives the same bytes.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x30A)
+    n = 500
+    lengths = (g.integers(0, 200, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    total = int(lengths.sum())
+    data = W.uniform_bytes(g, total)
+    offs, want, b = _run_batch(torch, keys, lengths, dirs, data)
+    x = torch.from_numpy(data).cuda()
+    out = torch.full_like(x, 0xA5)
+    _say("batch autotune")
+    m = b.autotune(x, out, reps=2)
+    assert m in (1, 2, 3, 4)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    out2 = torch.full_like(x, 0x5A)
+    b.submit(x, out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), want)
+    for i in range(0, n, 53):
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(want[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i

@@ -140,6 +140,22 @@ def test_cbc_argument_errors():
     assert call(nbytes=0, a=0, b=0) == 0
 
 
+def test_batch_autotune_argument_errors():
+    lib = T.lib()
+    m = ctypes.c_int(0)
+    a = ctypes.c_void_p(0x1000)
+
+    def call(n=4, reps=2, out=ctypes.byref(m), ws=0x1000, ws_bytes=1 << 20, msgs=0x1000):
+        return lib.tdes_batch_autotune(ctypes.c_void_p(msgs), n, a, 1, a, a, ctypes.c_void_p(ws),
+                                       ws_bytes, None, reps, out)
+    assert call(reps=0) == -1
+    assert call(out=None) == -1
+    assert call(n=0) == -1
+    assert call(ws_bytes=8) == -1       # workspace too small
+    assert call(ws=0x1004) == -3        # misaligned
+    assert call(msgs=0) == -1
+
+
 def _crypt_msg(n, a, b):
     _crypt(n, a, b)
     return T.lib().tdes_last_error()

@@ -3,7 +3,8 @@ host buffers out.  Two modes: direct (the kernel works on pinned host memory
 over PCIe) and staged (chunks through device slots on several streams).
 Every result is compared bit for bit with the oracle.  The cases are:
 
-* ragged sizes around chunk and wave-chunk boundaries;
+* ragged sizes around chunk and wave-chunk boundaries, and chunks off the
+  16-byte grid;
 * one slot (no overlap) and more slots than the library uses;
 * pinned and pageable memory, in place;
 * the 64 MiB case in full, in both directions and both modes;
@@ -54,6 +55,19 @@ def test_ragged_sizes_and_slot_counts(torch_dev, nbytes, n_slots):
     assert np.array_equal(got.numpy(), oracle.tdes_ecb(key, data))
     back = pipe.run(key, got, decrypt=True)
     assert np.array_equal(back.numpy(), data)
+
+
+def test_chunks_off_the_16_byte_grid(torch_dev):
+    # 8,008-byte chunks: every other slot starts 8 bytes off a 16-byte
+    # boundary (the kernel's 8-byte path), many chunks per slot, a short last one.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x515)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 8008 * 37 + 8 * 5)
+    pipe = T.HostPipeline(8008, 3)
+    _say("host path 8008-byte chunks")
+    got = pipe.run(key, _pinned(torch, data), decrypt=True)
+    assert np.array_equal(got.numpy(), oracle.tdes_ecb(key, data, decrypt=True))
 
 
 def test_pageable_and_in_place(torch_dev):

@@ -239,6 +239,8 @@ tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, vo
  * later tdes_batch_submit on the current device (and the request server's
  * batches); its multiplier is written to *grid_multiplier.  Synchronous.
  * The output is written several times, each time with the same result.
+ * Batched calls from other threads on the same device while it runs use
+ * the grid under trial (same results, other speed).
  * Errors: those of tdes_batch_submit, and TDES_ERR_ARG for reps < 1 or a
  * NULL grid_multiplier. */
 tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,

@@ -7,8 +7,9 @@ bitsliced (per 32 blocks = one lane):
   48 rounds x (S-box gates + 32 three-input XORs of the outputs into the other
   half, which also carry the key masks, + 16 key XORs of second-use inputs)
   + 4 transposes of 32 words (2 in, 2 out), each 16 pairs x
-    (2 + 2 + 4 + 4 + 4) ops (byte stages by v_perm_b32, bit stages by
-    shift + bit-field insert)
+    (2 + 2 + 4 + 4 + 4) ops (byte stages: one v_perm_b32 per word; bit
+    stages: two shifts, or a shift and an addition, and two v_bitop3_b32
+    selects per pair)
   IP, E, P and FP are register renaming: no operations.
 table (SP-box) kernel (per block):
   48 rounds x (1 rotate + 4 key XORs + 8 index extracts + 8 XORs)

@@ -8,8 +8,9 @@ directions, and the 1 GiB headline case in the launch configuration the
 benchmark times: seeded random positions checked one by one against the
 oracle, plus all-zero and repeating-pattern inputs whose every output block
 must equal the oracle's output on the one distinct input block.  Also: key
-bundles at the edges of the key material, a caller-named stream, and a
-buffer past 4 GiB (64-bit addressing).
+bundles at the edges of the key material, a caller-named stream, a buffer
+past 4 GiB (64-bit addressing), and the paper's one-thread-per-bit design
+(comparison kernel) against the oracle and the bitsliced kernel.
 """
 import sys
 

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define TDES_ABI_VERSION 1
+#define TDES_ABI_VERSION 2
 
 typedef enum {
     TDES_OK = 0,
@@ -165,17 +165,23 @@ size_t tdes_batch_workspace_bytes(size_t n_msgs);
 /* 3DES-EDE ECB over a batch of messages in one pass (the batched form of
  * tdes_ecb_crypt: per-message keys and directions, Sec. III-B; ECB, Sec. V).
  * d_msgs: n_msgs descriptors in device memory; d_schedules: n_schedules
- * entries written by tdes_schedule_upload; d_in_base / d_out_base: device
- * bases the message offsets refer to (8-byte aligned); d_workspace:
+ * entries written by tdes_schedule_upload or tdes_schedule_expand;
+ * d_in_base / d_out_base: device buffers of in_bytes / out_bytes bytes that
+ * the message offsets refer to (8-byte aligned); d_workspace:
  * tdes_batch_workspace_bytes(n_msgs) bytes of device memory (8-byte aligned),
  * overwritten.  Asynchronous on `stream`.  Message fields are checked on the
- * device: a message with a bad length, offset, schedule index or direction
- * is skipped, and the number skipped is left in the second 64-bit word of
- * the workspace.  Errors (synchronous): TDES_ERR_ARG (NULL pointers with
- * n_msgs > 0, workspace too small), TDES_ERR_ALIGN, TDES_ERR_DEVICE. */
+ * device: a message whose length or offsets are not multiples of 8, whose
+ * input range [in_off, in_off + nbytes) exceeds in_bytes or output range
+ * [out_off, out_off + nbytes) exceeds out_bytes, or whose schedule index or
+ * direction is out of range is skipped (neither read nor written), and the
+ * number skipped is left in the second 64-bit word of the workspace.
+ * Messages whose outputs overlap each other are not detected; their bytes
+ * are then unspecified.  Errors (synchronous): TDES_ERR_ARG (NULL pointers
+ * with n_msgs > 0, workspace too small), TDES_ERR_ALIGN, TDES_ERR_DEVICE. */
 tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
-                              size_t n_schedules, const void *d_in_base, void *d_out_base,
-                              void *d_workspace, size_t workspace_bytes, void *stream);
+                              size_t n_schedules, const void *d_in_base, size_t in_bytes,
+                              void *d_out_base, size_t out_bytes, void *d_workspace,
+                              size_t workspace_bytes, void *stream);
 
 /* ---- Host-resident form: data in host memory ----------------------------- */
 
@@ -238,14 +244,17 @@ tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, vo
  * timed with HIP events on `stream`.  The fastest grid is kept for every
  * later tdes_batch_submit on the current device (and the request server's
  * batches); its multiplier is written to *grid_multiplier.  Synchronous.
- * The output is written several times, each time with the same result.
- * Batched calls from other threads on the same device while it runs use
- * the grid under trial (same results, other speed).
- * Errors: those of tdes_batch_submit, and TDES_ERR_ARG for reps < 1 or a
- * NULL grid_multiplier. */
+ * Every trial reads the input and writes the output, so the input range
+ * [d_in_base, d_in_base + in_bytes) must not overlap the output range
+ * (TDES_ERR_OVERLAP otherwise, in-place batches included): each trial then
+ * writes the same result.  Batched calls from other threads on the same
+ * device while it runs use the grid under trial (same results, other
+ * speed).  Errors: those of tdes_batch_submit, TDES_ERR_OVERLAP, and
+ * TDES_ERR_ARG for reps < 1 or a NULL grid_multiplier. */
 tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
-                                size_t n_schedules, const void *d_in_base, void *d_out_base,
-                                void *d_workspace, size_t workspace_bytes, void *stream, int reps,
+                                size_t n_schedules, const void *d_in_base, size_t in_bytes,
+                                void *d_out_base, size_t out_bytes, void *d_workspace,
+                                size_t workspace_bytes, void *stream, int reps,
                                 int *grid_multiplier);
 
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or

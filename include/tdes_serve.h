@@ -53,6 +53,10 @@ typedef struct {
     uint32_t max_batch_msgs;  /* requests per batch, 1..65536                       */
     uint32_t test_polls;      /* HOST_TEST: progress calls a batch takes (>= 2)     */
     uint64_t max_batch_bytes; /* payload bytes per batch (0 = no limit)             */
+    uint32_t test_fail_batch; /* HOST_TEST: the launch of batch number
+                                 test_fail_batch - 1 fails as a HIP launch error
+                                 would (0 = never); for tests of the error path   */
+    uint32_t reserved;        /* 0                                                   */
 } tdes_server_config;
 
 typedef struct {
@@ -83,6 +87,7 @@ typedef struct {
     uint64_t arena_used_bytes, peak_arena_used_bytes;
     uint64_t batches, batched_msgs, batched_bytes;
     uint32_t busy_slots, peak_busy_slots;
+    uint64_t failed;          /* completed with a device error (no result)          */
 } tdes_server_stats;
 
 /* Create a server.  Errors: TDES_ERR_ARG (bad config), TDES_ERR_ALIGN,
@@ -101,7 +106,11 @@ tdes_status tdes_server_submit(tdes_server *s, const tdes_request *reqs, size_t 
 
 /* Non-blocking step: retire finished batches, admit queued requests and
  * launch batches on free slots, then hand out up to cap completions
- * (*n_out of them).  Errors: TDES_ERR_ARG, TDES_ERR_DEVICE. */
+ * (*n_out of them).  If HIP reports an error for a batch (its launch, or
+ * the query of its completion), every request of that batch completes with
+ * status TDES_ERR_DEVICE and no result (d_out NULL, nothing to release):
+ * its budget and arena space are given back at once, and tdes_last_error()
+ * holds HIP's message.  Errors: TDES_ERR_ARG. */
 tdes_status tdes_server_progress(tdes_server *s, tdes_completion *out, size_t cap, size_t *n_out);
 
 /* Give back the arena space of a completed request (its d_out).

@@ -240,8 +240,9 @@ tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, vo
 size_t tdes_batch_workspace_bytes(size_t n_msgs) { return tdes::batch_workspace_bytes(n_msgs); }
 
 tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
-                              size_t n_schedules, const void *d_in_base, void *d_out_base,
-                              void *d_workspace, size_t workspace_bytes, void *stream) {
+                              size_t n_schedules, const void *d_in_base, size_t in_bytes,
+                              void *d_out_base, size_t out_bytes, void *d_workspace,
+                              size_t workspace_bytes, void *stream) {
     g_last_error.clear();
     if (n_msgs == 0) return TDES_OK;
     tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
@@ -249,16 +250,17 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
     if (st != TDES_OK) return st;
     hipError_t e = tdes::launch_batch(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
                                       n_schedules, static_cast<const uint8_t *>(d_in_base),
-                                      static_cast<uint8_t *>(d_out_base),
-                                      static_cast<uint64_t *>(d_workspace),
+                                      in_bytes, static_cast<uint8_t *>(d_out_base), out_bytes,
+                                      static_cast<uint64_t *>(d_workspace), nullptr,
                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
     return TDES_OK;
 }
 
 tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
-                                size_t n_schedules, const void *d_in_base, void *d_out_base,
-                                void *d_workspace, size_t workspace_bytes, void *stream, int reps,
+                                size_t n_schedules, const void *d_in_base, size_t in_bytes,
+                                void *d_out_base, size_t out_bytes, void *d_workspace,
+                                size_t workspace_bytes, void *stream, int reps,
                                 int *grid_multiplier) {
     g_last_error.clear();
     if (reps < 1 || grid_multiplier == nullptr)
@@ -268,9 +270,15 @@ tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const voi
     tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
                                               d_out_base, d_workspace, workspace_bytes);
     if (st != TDES_OK) return st;
+    // every trial rewrites the output from the input: they must not alias,
+    // or each trial would encrypt the previous trial's result again
+    const uintptr_t a = (uintptr_t)d_in_base, b = (uintptr_t)d_out_base;
+    if (in_bytes > 0 && out_bytes > 0 && a < b + out_bytes && b < a + in_bytes)
+        return fail(TDES_ERR_OVERLAP,
+                    "autotuning runs the batch several times: input and output must not overlap");
     hipError_t e = tdes::batch_autotune(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
                                         n_schedules, static_cast<const uint8_t *>(d_in_base),
-                                        static_cast<uint8_t *>(d_out_base),
+                                        in_bytes, static_cast<uint8_t *>(d_out_base), out_bytes,
                                         static_cast<uint64_t *>(d_workspace),
                                         static_cast<hipStream_t>(stream), reps, grid_multiplier);
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "autotune failed: %s", hipGetErrorString(e));

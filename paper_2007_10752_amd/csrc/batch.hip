@@ -41,10 +41,19 @@ constexpr int kScanThreads = 1024;
 // [2 + i] first slice of message i (i = 0..n; entry n = total).
 constexpr int kWsHeader = 2;
 
-__device__ __forceinline__ uint64_t slices_of(const tdes_msg &m, size_t n_sched, bool *bad) {
-    // bitwise, not short-circuit, so that no field is read under a branch
+// Buffer sizes a batch's message ranges are checked against.
+struct BatchBounds {
+    uint64_t in_bytes, out_bytes;
+};
+
+__device__ __forceinline__ uint64_t slices_of(const tdes_msg &m, size_t n_sched, BatchBounds bb,
+                                              bool *bad) {
+    // bitwise, not short-circuit, so that no field is read under a branch;
+    // in_bytes - nbytes may wrap, but only where nbytes <= in_bytes fails
     const bool ok = (((m.nbytes | m.in_off | m.out_off) % 8) == 0) & (m.sched_idx < n_sched) &
-                    (m.dir <= 1);
+                    (m.dir <= 1) & (m.nbytes <= bb.in_bytes) &
+                    (m.in_off <= bb.in_bytes - m.nbytes) & (m.nbytes <= bb.out_bytes) &
+                    (m.out_off <= bb.out_bytes - m.nbytes);
     *bad = !ok;
     return ok ? (m.nbytes + kSlice - 1) / kSlice : 0;
 }
@@ -69,7 +78,9 @@ __device__ __forceinline__ uint64_t wave_scan(uint64_t v, int lane) {
 constexpr int kScanSteps = 8;  // 64-descriptor steps per wave and chunk
 
 __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg *msgs, size_t n,
-                                                                 size_t n_sched, uint64_t *ws) {
+                                                                 size_t n_sched, BatchBounds bb,
+                                                                 uint64_t *ws,
+                                                                 uint64_t *skipped_out) {
     constexpr int kWaves = kScanThreads / kWave;
     constexpr size_t kWaveMsgs = (size_t)kWave * kScanSteps;
     constexpr size_t kChunkMsgs = kWaveMsgs * kWaves;
@@ -87,7 +98,7 @@ __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg
             const size_t i = wbase + (size_t)k * kWave + lane;
             const tdes_msg m = msgs[i < n ? i : n - 1];
             bool bad = false;
-            const uint64_t vi = slices_of(m, n_sched, &bad);
+            const uint64_t vi = slices_of(m, n_sched, bb, &bad);
             const uint64_t v = i < n ? vi : 0;
             nbad += (bad && i < n) ? 1u : 0u;
             const uint64_t incl = wave_scan(v, lane);
@@ -120,6 +131,7 @@ __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg
         ws[0] = run;
         ws[1] = bad_total;
         ws[kWsHeader + n] = run;
+        if (skipped_out != nullptr) *skipped_out = bad_total;
     }
 }
 
@@ -281,17 +293,20 @@ int current_device() {
     return hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices ? dev : 0;
 }
 
+// Workgroups of the batched kernel that fit on the current device at once,
+// cached per device.
+std::atomic<int> g_resident[kMaxDevices];
+
 int resident_blocks() {
-    static std::atomic<int> n{0};
-    int v = n.load();
+    const int dev = current_device();
+    int v = g_resident[dev].load();
     if (v == 0) {
         int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, current_device()) !=
-                hipSuccess ||
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
         v = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock;  // 4 SIMDs per CU
-        n.store(v);
+        g_resident[dev].store(v);
     }
     return v;
 }
@@ -320,20 +335,24 @@ hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint
 }
 
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
-                          size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
-                          hipStream_t stream, int reps, int *mult_out) {
+                          size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
+                          uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
+                          int *mult_out) {
     const int dev = current_device();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     float best_ms = 0;
     int best = TDES_BATCH_GRID_MULT;
+    auto run = [&]() {
+        return launch_batch(msgs, n_msgs, schedules, n_schedules, in, in_bytes, out, out_bytes, ws,
+                            nullptr, stream);
+    };
     for (int m = 1; m <= kMaxGridMult && e == hipSuccess; m++) {
         g_tuned_mult[dev].store(m);
-        e = launch_batch(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);  // warm
+        e = run();  // warm
         if (e == hipSuccess) e = hipEventRecord(a, stream);
-        for (int r = 0; r < reps && e == hipSuccess; r++)
-            e = launch_batch(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = run();
         if (e == hipSuccess) e = hipEventRecord(b, stream);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0;
@@ -353,10 +372,11 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
 size_t batch_workspace_bytes(size_t n_msgs) { return (kWsHeader + n_msgs + 1) * sizeof(uint64_t); }
 
 hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
-                        size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
+                        size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
+                        uint64_t out_bytes, uint64_t *ws, uint64_t *skipped_out,
                         hipStream_t stream) {
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, msgs, n_msgs,
-                       n_schedules, ws);
+                       n_schedules, BatchBounds{in_bytes, out_bytes}, ws, skipped_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batch_bitslice_kernel, dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,

@@ -77,16 +77,21 @@ hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, h
 hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                                  size_t n_schedules, const uint8_t *in, uint8_t *out,
                                  const uint64_t *ws, hipStream_t stream);
+// Descriptor scan (validation against the buffer sizes, first-slice table in
+// ws, skipped count in ws[1] and, if skipped_out is not NULL, there too),
+// then the batched cipher.
 hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
-                        size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
+                        size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
+                        uint64_t out_bytes, uint64_t *ws, uint64_t *skipped_out,
                         hipStream_t stream);
 // Times the batch (scan + cipher, `reps` runs after one warm run) at grids
 // of 1..4 times the resident workgroups on `stream`, keeps the fastest for
 // later batched launches on the current device and returns its multiplier.
 // Synchronous.
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
-                          size_t n_schedules, const uint8_t *in, uint8_t *out, uint64_t *ws,
-                          hipStream_t stream, int reps, int *mult_out);
+                          size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
+                          uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
+                          int *mult_out);
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 

@@ -147,6 +147,27 @@ void complete(tdes_server *s, const Active &a, uint32_t batch, double t_launch, 
     s->st.completed++;
 }
 
+// A request whose batch failed on the device: it completes with `status`
+// and no result, and its budget and arena range are given back at once.
+void complete_failed(tdes_server *s, const Active &a, uint32_t batch, double t_launch,
+                     int32_t status) {
+    tdes_completion c{};
+    c.tag = a.req.tag;
+    c.nbytes = a.req.nbytes;
+    c.status = status;
+    c.batch = batch;
+    c.t_submit = a.t_submit;
+    c.t_admit = a.t_admit;
+    c.t_launch = t_launch;
+    c.t_done = now_s();
+    s->done.push_back(c);
+    s->arena.release(a.out_off, a.out_bytes);
+    s->st.in_flight_bytes -= a.req.nbytes + a.out_bytes;
+    s->st.arena_used_bytes = s->arena.used();
+    s->st.completed++;
+    s->st.failed++;
+}
+
 void reject(tdes_server *s, const tdes_request &r, double t, int32_t status) {
     tdes_completion c{};
     c.tag = r.tag;
@@ -191,7 +212,9 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
     for (const Active &a : sl.reqs) s->st.batched_bytes += a.req.nbytes;
     if (!s->device) {
         sl.polls_left = s->cfg.test_polls > 1 ? s->cfg.test_polls - 1 : 1;
-        return TDES_OK;
+        return s->cfg.test_fail_batch == sl.batch + 1
+                   ? fail(TDES_ERR_DEVICE, "injected launch failure (host test mode)")
+                   : TDES_OK;
     }
     hipError_t e;
     if (n == 1) {
@@ -241,6 +264,17 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
     return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
 }
 
+// Every request of the slot's batch fails (launch or completion query
+// error).  The slot's stream is drained first, so work already enqueued for
+// the batch cannot touch the staging area or the arena after the slot and
+// the requests' output ranges are reused.
+void fail_slot(tdes_server *s, Slot &sl) {
+    if (s->device && sl.stream) (void)hipStreamSynchronize(sl.stream);
+    for (const Active &a : sl.reqs) complete_failed(s, a, sl.batch, sl.t_launch, TDES_ERR_DEVICE);
+    sl.reqs.clear();
+    sl.busy = false;
+}
+
 tdes_status progress_batched(tdes_server *s) {
     uint32_t busy = 0;
     for (Slot &sl : s->slots) {  // retire
@@ -248,8 +282,11 @@ tdes_status progress_batched(tdes_server *s) {
         bool finished;
         if (s->device) {
             const hipError_t q = hipEventQuery(sl.done);
-            if (q != hipSuccess && q != hipErrorNotReady)
-                return fail(TDES_ERR_DEVICE, hipGetErrorString(q));
+            if (q != hipSuccess && q != hipErrorNotReady) {
+                fail(TDES_ERR_DEVICE, hipGetErrorString(q));
+                fail_slot(s, sl);
+                continue;
+            }
             finished = q == hipSuccess;
         } else {
             finished = sl.polls_left <= 1;
@@ -277,8 +314,10 @@ tdes_status progress_batched(tdes_server *s) {
             sl.reqs.push_back(a);
         }
         if (sl.reqs.empty()) break;  // nothing admissible: later slots stay free too
-        tdes_status r = launch_slot(s, sl);
-        if (r != TDES_OK) return r;
+        if (launch_slot(s, sl) != TDES_OK) {
+            fail_slot(s, sl);
+            continue;
+        }
         busy++;
     }
     s->st.busy_slots = busy;
@@ -291,8 +330,13 @@ tdes_status progress_plain(tdes_server *s) {
         PlainEntry &p = s->plain.front();
         const hipError_t q = hipEventQuery(p.ev);
         if (q == hipErrorNotReady) break;
-        if (q != hipSuccess) return fail(TDES_ERR_DEVICE, hipGetErrorString(q));
-        complete(s, p.a, p.seq, p.t_launch, now_s(), TDES_OK);
+        if (q != hipSuccess) {
+            fail(TDES_ERR_DEVICE, hipGetErrorString(q));
+            (void)hipStreamSynchronize(s->plain_stream);
+            complete_failed(s, p.a, p.seq, p.t_launch, TDES_ERR_DEVICE);
+        } else {
+            complete(s, p.a, p.seq, p.t_launch, now_s(), TDES_OK);
+        }
         s->plain_events.push_back(p.ev);
         s->plain.pop_front();
     }
@@ -309,7 +353,13 @@ tdes_status progress_plain(tdes_server *s) {
                                              static_cast<uint8_t *>(s->cfg.d_arena) + a.out_off,
                                              a.req.nbytes, s->plain_stream);
         if (e == hipSuccess) e = hipEventRecord(p.ev, s->plain_stream);
-        if (e != hipSuccess) return fail(TDES_ERR_DEVICE, hipGetErrorString(e));
+        if (e != hipSuccess) {  // the request fails; its event goes back to the pool
+            fail(TDES_ERR_DEVICE, hipGetErrorString(e));
+            (void)hipStreamSynchronize(s->plain_stream);
+            complete_failed(s, a, p.seq, p.t_launch, TDES_ERR_DEVICE);
+            s->plain_events.push_back(p.ev);
+            continue;
+        }
         s->plain.push_back(p);
         s->st.batches++;
         s->st.batched_msgs++;

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "generated/spbox_gen.h"
 #include "internal.h"
 
@@ -86,15 +88,23 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in,
     }
 }
 
+// Workgroups that fit on the current device at once, cached per device
+// (atomics: first calls from several threads may race; they all store the
+// same value).
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_resident[kMaxDevices];
+
 int resident_workgroups() {
-    static int n = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    int n = g_resident[dev].load();
     if (n == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
         n = 2 * cus;  // 64 KiB of tables per workgroup: two fit in 160 KiB of LDS
+        g_resident[dev].store(n);
     }
     return n;
 }

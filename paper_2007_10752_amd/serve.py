@@ -21,7 +21,8 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("d_arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
                 ("budget_bytes", ctypes.c_uint64), ("mode", ctypes.c_uint32),
                 ("slots", ctypes.c_uint32), ("max_batch_msgs", ctypes.c_uint32),
-                ("test_polls", ctypes.c_uint32), ("max_batch_bytes", ctypes.c_uint64)]
+                ("test_polls", ctypes.c_uint32), ("max_batch_bytes", ctypes.c_uint64),
+                ("test_fail_batch", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -29,7 +30,8 @@ class ServerStats(ctypes.Structure):
         "submitted", "admitted", "completed", "released", "rejected", "queued",
         "in_flight_bytes", "peak_in_flight_bytes", "arena_used_bytes", "peak_arena_used_bytes",
         "batches", "batched_msgs", "batched_bytes")] + [
-        ("busy_slots", ctypes.c_uint32), ("peak_busy_slots", ctypes.c_uint32)]
+        ("busy_slots", ctypes.c_uint32), ("peak_busy_slots", ctypes.c_uint32),
+        ("failed", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -78,11 +80,12 @@ class Server:
     (a fake, never-dereferenced address is fine in HOST_TEST mode)."""
 
     def __init__(self, arena_ptr, arena_bytes, budget_bytes=0, mode=BATCHED, slots=4,
-                 max_batch_msgs=4096, max_batch_bytes=0, test_polls=2, completion_cap=65536):
+                 max_batch_msgs=4096, max_batch_bytes=0, test_polls=2, completion_cap=65536,
+                 test_fail_batch=0):
         self.h = None
         L = _lib()
         cfg = ServerConfig(arena_ptr, arena_bytes, budget_bytes, mode, slots, max_batch_msgs,
-                           test_polls, max_batch_bytes)
+                           test_polls, max_batch_bytes, test_fail_batch, 0)
         h = ctypes.c_void_p()
         tdes._check(L.tdes_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h

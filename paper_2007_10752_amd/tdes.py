@@ -78,10 +78,10 @@ def lib():
         L.tdes_schedule_expand.restype = ctypes.c_int
         L.tdes_batch_workspace_bytes.argtypes = [sz]
         L.tdes_batch_workspace_bytes.restype = sz
-        L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp]
+        L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp]
         L.tdes_batch_submit.restype = ctypes.c_int
-        L.tdes_batch_autotune.argtypes = [vp, sz, vp, sz, vp, vp, vp, sz, vp, ctypes.c_int,
-                                          ctypes.POINTER(ctypes.c_int)]
+        L.tdes_batch_autotune.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.tdes_batch_autotune.restype = ctypes.c_int
         L.tdes_ctr_crypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
         L.tdes_ctr_crypt.restype = ctypes.c_int
@@ -334,11 +334,13 @@ def batch_workspace_bytes(n_msgs):
     return int(lib().tdes_batch_workspace_bytes(n_msgs))
 
 
-def batch_submit_ptr(d_msgs, n_msgs, d_sched, n_sched, d_in, d_out, d_ws, ws_bytes, stream=0):
+def batch_submit_ptr(d_msgs, n_msgs, d_sched, n_sched, d_in, in_bytes, d_out, out_bytes, d_ws,
+                     ws_bytes, stream=0):
     """tdes_batch_submit on raw device addresses."""
     _check(lib().tdes_batch_submit(ctypes.c_void_p(d_msgs), n_msgs, ctypes.c_void_p(d_sched),
-                                   n_sched, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
-                                   ctypes.c_void_p(d_ws), ws_bytes, ctypes.c_void_p(stream)))
+                                   n_sched, ctypes.c_void_p(d_in), in_bytes,
+                                   ctypes.c_void_p(d_out), out_bytes, ctypes.c_void_p(d_ws),
+                                   ws_bytes, ctypes.c_void_p(stream)))
 
 
 def msg_table(in_off, out_off, nbytes, sched_idx, dirs):
@@ -375,20 +377,23 @@ class Batch:
         self.ws = torch.empty((self.ws_bytes + 7) // 8, dtype=torch.int64, device="cuda")
 
     def submit(self, x, out, stream=None):
-        """Run the batch over input base x and output base out (uint8 CUDA tensors)."""
+        """Run the batch over input base x and output base out (uint8 CUDA
+        tensors; message ranges are checked against their sizes)."""
         batch_submit_ptr(self.msgs.data_ptr(), self.n_msgs, self.sched.data_ptr(), self.n_sched,
-                         x.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                         x.data_ptr(), x.numel(), out.data_ptr(), out.numel(),
+                         self.ws.data_ptr(), self.ws_bytes,
                          _stream_handle(stream) if stream is not None else self.stream)
         return out
 
     def autotune(self, x, out, reps=3, stream=None):
         """Time this batch at grids of 1..4 times the resident workgroups and
         keep the fastest for later batched launches on this device; returns
-        the chosen multiplier (synchronous)."""
+        the chosen multiplier (synchronous).  x and out must not overlap."""
         m = ctypes.c_int(0)
         _check(lib().tdes_batch_autotune(
             ctypes.c_void_p(self.msgs.data_ptr()), self.n_msgs, ctypes.c_void_p(self.sched.data_ptr()),
-            self.n_sched, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            self.n_sched, ctypes.c_void_p(x.data_ptr()), x.numel(),
+            ctypes.c_void_p(out.data_ptr()), out.numel(),
             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
             ctypes.c_void_p(_stream_handle(stream) if stream is not None else self.stream),
             int(reps), ctypes.byref(m)))

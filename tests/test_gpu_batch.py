@@ -276,3 +276,53 @@ def test_batch_autotune_keeps_results(torch_dev):
     for i in range(0, n, 53):
         seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
         assert np.array_equal(want[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
+def test_out_of_range_messages_are_skipped(torch_dev):
+    # Message ranges are checked against the input and output buffer sizes:
+    # a message reaching past either end (including offsets that would wrap
+    # a 64-bit sum) is skipped and counted, and nothing past the declared
+    # output size is written.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x30B)
+    keys = W.key_bundles(g, 6)
+    data = W.uniform_bytes(g, 8192)
+    x = torch.from_numpy(data).cuda()
+    big = torch.full((8192 + 4096,), 0x3C, dtype=torch.uint8, device="cuda")
+    out = big[:8192]
+    in_off = [0, 4096, 8192 - 512, 1024, (1 << 64) - 8, 2048]
+    out_off = [0, 4096, 2048, 8192 - 256, 512, (1 << 64) - 1024]
+    lengths = [1024, 1024, 1024, 512, 64, 1024]
+    # 2: input past the end; 3: output past the end; 4: input offset wraps;
+    # 5: output offset wraps
+    b = T.Batch(keys, np.array(in_off, dtype=np.uint64).astype(np.int64),
+                np.array(out_off, dtype=np.uint64).astype(np.int64), lengths, [0, 1, 0, 0, 0, 0])
+    b.submit(x, out)
+    torch.cuda.synchronize()
+    assert b.skipped() == 4
+    got = big.cpu().numpy()
+    assert np.array_equal(got[:1024], oracle.tdes_ecb(keys[0], data[:1024]))
+    assert np.array_equal(got[4096:5120], oracle.tdes_ecb(keys[1], data[4096:5120], True))
+    untouched = np.ones(got.size, bool)
+    untouched[:1024] = False
+    untouched[4096:5120] = False
+    assert (got[untouched] == 0x3C).all()
+
+
+def test_autotune_refuses_aliasing_buffers(torch_dev):
+    # Every trial of the autotuner rewrites the output from the input, so an
+    # in-place batch would be encrypted once per trial: it is refused.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x30C)
+    n = 40
+    lengths = (g.integers(1, 100, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    data = W.uniform_bytes(g, int(lengths.sum()))
+    offs, want, b = _run_batch(torch, keys, lengths, dirs, data)
+    x = torch.from_numpy(data).cuda()
+    with pytest.raises(T.TdesError) as e:
+        b.autotune(x, x, reps=1)
+    assert e.value.status == -4
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), data)  # nothing ran

@@ -5,13 +5,17 @@ Sizes: the 32 KiB case (encrypt then decrypt), ragged sizes around the
 16 KiB wave chunk and the 32-block lane slice, unaligned and in-place
 buffers, the 64 MiB case in full for 3-key and 2-key bundles in both
 directions, and the 1 GiB headline case in the launch configuration the
-benchmark times: seeded random positions checked one by one against the
-oracle, plus all-zero and repeating-pattern inputs whose every output block
-must equal the oracle's output on the one distinct input block.  Also: key
+benchmark times: the whole output against the SHA-256 of the oracle's output
+on the same seeded input (tests/golden, written by a script that calls only
+the oracle), seeded random positions checked one by one against the oracle,
+plus all-zero and repeating-pattern inputs whose every output block must
+equal the oracle's output on the one distinct input block.  Also: key
 bundles at the edges of the key material, a caller-named stream, a buffer
 past 4 GiB (64-bit addressing), and the paper's one-thread-per-bit design
 (comparison kernel) against the oracle and the bitsliced kernel.
 """
+import hashlib
+import os
 import sys
 
 import numpy as np
@@ -142,16 +146,38 @@ def test_64mib_full(torch_dev, kernel, two_key):
 GIB = 1 << 30
 
 
+def _golden_1gib():
+    """Fields of tests/golden/ecb_1gib_digest.txt (written by the oracle)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "ecb_1gib_digest.txt")
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                fields[k] = v
+    return fields
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_1gib_sampled_and_structured(torch_dev, kernel):
+def test_1gib_full_and_structured(torch_dev, kernel):
+    # The whole 1 GiB uniform output (134,217,728 blocks) against the SHA-256
+    # of the oracle's output on the same seeded input, plus a seeded sample
+    # and the first and last wave chunks compared block by block.
     torch = torch_dev
-    g = W.rng(W.SEED_BASE + 2)
-    key = W.key_bundle(W.rng(W.SEED_BASE + 2 + W.KEY_SEED_OFFSET))
+    gold = _golden_1gib()
+    g = W.rng(int(gold["data_seed"]))
+    key = W.key_bundle(W.rng(int(gold["key_seed"])))
+    assert bytes(key).hex() == gold["key24"]
     _say("1GiB uniform", kernel)
-    x = torch.from_numpy(W.uniform_bytes(g, GIB)).cuda()
+    data = W.uniform_bytes(g, GIB)
+    assert hashlib.sha256(data.tobytes()).hexdigest() == gold["input_sha256"]
+    x = torch.from_numpy(data).cuda()
+    del data
     out = torch.empty_like(x)
     T.encrypt(key, x, out, kernel=kernel)
     torch.cuda.synchronize()
+    assert hashlib.sha256(out.cpu().numpy().tobytes()).hexdigest() == gold["encrypt_sha256"]
     nblk = GIB // 8
     idx = W.rng(W.SEED_BASE + 0x60).choice(nblk, 1 << 16, replace=False)
     idx = np.concatenate([np.arange(2048), idx, np.arange(nblk - 2048, nblk)])

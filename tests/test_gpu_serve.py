@@ -37,18 +37,27 @@ def _server(env, **kw):
 
 
 def _run(env, srv, reqs, arrival, capture):
+    """Serve the trace; keep a device copy of the results whose tags are in
+    capture (None: all) and the batch number each request ran in."""
     torch, pool, arena, pad = env
-    got = {}
+    got, batch_of = {}, {}
 
     def keep(comp):
+        copied = False
         for c in comp:
             t = int(c["tag"])
-            if t in capture and c["status"] == 0:
+            batch_of[t] = int(c["batch"])
+            if (capture is None or t in capture) and c["status"] == 0:
                 off = int(c["d_out"]) - arena.data_ptr()
-                got[t] = arena[off: off + int(c["nbytes"])].cpu().numpy()
+                got[t] = arena[off: off + int(c["nbytes"])].clone()
+                copied = True
+        if copied:
+            # the driver releases these results next: the copies (on torch's
+            # stream) must be done before the server reuses their arena space
+            torch.cuda.current_stream().synchronize()
 
     lat, status, wall, st = S.run_open_loop(srv, reqs, arrival, on_complete=keep)
-    return got, lat, status, st
+    return got, lat, status, st, batch_of
 
 
 def _pool_bytes(env, r):
@@ -63,23 +72,35 @@ def test_mixed_equals_alone_and_oracle(env, mode):
     trace = W.serving_trace(W.SEED_BASE + 5, rate=20000, duration_s=0.15, bands=SMALL_BANDS)
     reqs = S.make_requests(trace, pool.data_ptr(), pool.numel(), W.SEED_BASE + 6)
     n = len(reqs)
-    capture = set(W.rng(W.SEED_BASE + 7).choice(n, 48, replace=False).tolist())
-    capture |= {int(np.argmax(trace["size"]))}
     _say("serve mix mode", mode, n, "requests")
     srv = _server(env, mode=mode, slots=4, max_batch_msgs=1024)
-    got, lat, status, st = _run(env, srv, reqs, trace["arrival"], capture)
+    got, lat, status, st, batch_of = _run(env, srv, reqs, trace["arrival"], None)
     srv.close()
     assert (status == 0).all()
     assert st["completed"] == n and st["released"] == n and st["in_flight_bytes"] == 0
+    # checked: requests that shared a batch with others (in batched mode the
+    # batch kernel ran them, the property continuous batching must keep),
+    # requests that ran alone, and the largest request
+    size = {}
+    for b in batch_of.values():
+        size[b] = size.get(b, 0) + 1
+    shared = [t for t in range(n) if size[batch_of[t]] > 1]
+    single = [t for t in range(n) if size[batch_of[t]] == 1]
+    pick = W.rng(W.SEED_BASE + 7)
+    capture = set(pick.choice(shared, min(40, len(shared)), replace=False).tolist()) if shared else set()
+    capture |= set(pick.choice(single, min(8, len(single)), replace=False).tolist()) if single else set()
+    capture |= {int(np.argmax(trace["size"]))}
     if mode == S.BATCHED:
         assert st["batches"] < n                 # requests really were batched
+        assert len(shared) >= 40, len(shared)    # and the check covers batch-kernel output
     alone = _server(env, mode=S.BATCHED, slots=1, max_batch_msgs=1)
     for t in sorted(capture):
-        one, _, st1, _ = _run(env, alone, reqs[t:t + 1], np.zeros(1), {0})
+        one, _, st1, _, _ = _run(env, alone, reqs[t:t + 1], np.zeros(1), {0})
         assert (st1 == 0).all()
-        assert np.array_equal(one[0], got[t]), t
+        mine = got[t].cpu().numpy()
+        assert np.array_equal(one[0].cpu().numpy(), mine), t
         want = oracle.tdes_ecb(trace["keys"][t], _pool_bytes(env, reqs[t]), bool(trace["dirs"][t]))
-        assert np.array_equal(got[t], want), t
+        assert np.array_equal(mine, want), t
     alone.close()
 
 
@@ -89,7 +110,7 @@ def test_budget_holds_under_load(env):
     torch, pool, arena, pad = env
     reqs = S.make_requests(trace, pool.data_ptr(), pool.numel(), W.SEED_BASE + 9)
     srv = _server(env, budget_bytes=budget, slots=4, max_batch_msgs=256)
-    _, lat, status, st = _run(env, srv, reqs, trace["arrival"], set())
+    _, lat, status, st, _ = _run(env, srv, reqs, trace["arrival"], set())
     srv.close()
     assert (status == 0).all()
     assert st["peak_in_flight_bytes"] <= budget

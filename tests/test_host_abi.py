@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol():
     assert sorted(T.SYMBOLS) == declared
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.tdes_abi_version() == 1
+    assert lib.tdes_abi_version() == 2
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -145,14 +145,38 @@ def test_batch_autotune_argument_errors():
     m = ctypes.c_int(0)
     a = ctypes.c_void_p(0x1000)
 
-    def call(n=4, reps=2, out=ctypes.byref(m), ws=0x1000, ws_bytes=1 << 20, msgs=0x1000):
-        return lib.tdes_batch_autotune(ctypes.c_void_p(msgs), n, a, 1, a, a, ctypes.c_void_p(ws),
-                                       ws_bytes, None, reps, out)
+    def call(n=4, reps=2, out=ctypes.byref(m), ws=0x1000, ws_bytes=1 << 20, msgs=0x1000,
+             d_in=0x100000, in_bytes=4096, d_out=0x200000, out_bytes=4096):
+        return lib.tdes_batch_autotune(ctypes.c_void_p(msgs), n, a, 1, ctypes.c_void_p(d_in),
+                                       in_bytes, ctypes.c_void_p(d_out), out_bytes,
+                                       ctypes.c_void_p(ws), ws_bytes, None, reps, out)
     assert call(reps=0) == -1
     assert call(out=None) == -1
     assert call(n=0) == -1
     assert call(ws_bytes=8) == -1       # workspace too small
     assert call(ws=0x1004) == -3        # misaligned
+    assert call(msgs=0) == -1
+    # the trials rewrite the output from the input: aliasing is refused
+    assert call(d_out=0x100000) == -4   # in place
+    assert b"must not overlap" in lib.tdes_last_error()
+    assert call(d_out=0x100800) == -4   # partial overlap
+    assert call(d_in=0x200800) == -4    # output range covers the input's start
+
+
+def test_batch_submit_argument_errors():
+    lib = T.lib()
+    a = ctypes.c_void_p(0x1000)
+
+    def call(n=4, ws=0x1000, ws_bytes=1 << 20, msgs=0x1000, sched=0x1000, n_sched=1, d_in=0x100000):
+        return lib.tdes_batch_submit(ctypes.c_void_p(msgs), n, ctypes.c_void_p(sched), n_sched,
+                                     ctypes.c_void_p(d_in), 4096, a, 4096, ctypes.c_void_p(ws),
+                                     ws_bytes, None)
+    assert call(n=0, msgs=0, ws=0) == 0  # empty batch: no-op
+    assert call(ws_bytes=8) == -1
+    assert b"workspace too small" in lib.tdes_last_error()
+    assert call(n_sched=0) == -1
+    assert call(sched=0x1008) == -3     # schedules must be 16-byte aligned
+    assert call(d_in=0x100004) == -3
     assert call(msgs=0) == -1
 
 

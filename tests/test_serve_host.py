@@ -139,3 +139,36 @@ def test_open_loop_driver_in_host_mode():
     lat, status, wall, st = S.run_open_loop(s, reqs, arrival)
     assert (status == 0).all() and not np.isnan(lat).any()
     assert st["completed"] == n and st["released"] == n and st["in_flight_bytes"] == 0
+
+
+def test_failed_launch_completes_its_requests_with_an_error():
+    # A batch whose launch fails: its requests complete with
+    # TDES_ERR_DEVICE and no result, their budget and arena space come back
+    # at once, the slot is free again, and later batches run normally.
+    s = _server(slots=1, max_batch_msgs=4, test_polls=2, test_fail_batch=2)
+    s.submit(_reqs([512] * 4))
+    s.progress()                              # batch 0 launched
+    c0 = s.progress()                         # batch 0 done
+    assert (c0["status"] == 0).all() and len(c0) == 4
+    s.submit(_reqs([512] * 3, base=1 << 34))
+    c1 = s.progress()                         # batch 1's launch fails
+    assert len(c1) == 3
+    assert (c1["status"] == -6).all() and (c1["d_out"] == 0).all() and (c1["batch"] == 1).all()
+    assert b"injected launch failure" in T.lib().tdes_last_error()
+    st = s.stats()
+    assert st["failed"] == 3 and st["busy_slots"] == 0
+    # only batch 0's outputs are still held
+    assert st["in_flight_bytes"] == 4 * 512 and st["arena_used_bytes"] == 4 * 512
+    with pytest.raises(T.TdesError):
+        s.release(int(c1["d_out"][0]) or 1)
+    for d in c0["d_out"]:
+        s.release(d)
+    s.submit(_reqs([512] * 2, base=1 << 35))
+    s.progress()                              # batch 2 runs
+    c2 = s.progress()
+    assert len(c2) == 2 and (c2["status"] == 0).all() and (c2["batch"] == 2).all()
+    for d in c2["d_out"]:
+        s.release(d)
+    st = s.stats()
+    assert st["in_flight_bytes"] == 0 and st["arena_used_bytes"] == 0
+    assert st["completed"] == 9 and st["failed"] == 3

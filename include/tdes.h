@@ -159,6 +159,10 @@ tdes_status tdes_schedule_upload(const tdes_schedule *h, size_t n, void *d_dst, 
  * TDES_ERR_ARG, TDES_ERR_ALIGN, TDES_ERR_DEVICE. */
 tdes_status tdes_schedule_expand(const void *d_keys24, size_t n, void *d_schedules, void *stream);
 
+/* Most messages and schedules one batched call takes (TDES_ERR_ARG beyond). */
+#define TDES_BATCH_MAX_MSGS (1u << 31)
+#define TDES_BATCH_MAX_SCHEDULES (1u << 22)
+
 /* Device workspace bytes tdes_batch_submit needs for n_msgs messages. */
 size_t tdes_batch_workspace_bytes(size_t n_msgs);
 
@@ -177,7 +181,9 @@ size_t tdes_batch_workspace_bytes(size_t n_msgs);
  * number skipped is left in the second 64-bit word of the workspace.
  * Messages whose outputs overlap each other are not detected; their bytes
  * are then unspecified.  Errors (synchronous): TDES_ERR_ARG (NULL pointers
- * with n_msgs > 0, workspace too small), TDES_ERR_ALIGN, TDES_ERR_DEVICE. */
+ * with n_msgs > 0, workspace too small, n_msgs > TDES_BATCH_MAX_MSGS,
+ * n_schedules 0 or > TDES_BATCH_MAX_SCHEDULES), TDES_ERR_ALIGN,
+ * TDES_ERR_DEVICE. */
 tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
                               size_t n_schedules, const void *d_in_base, size_t in_bytes,
                               void *d_out_base, size_t out_bytes, void *d_workspace,

@@ -45,6 +45,12 @@ tdes_status tdes_batch_submit_checks(const tdes_msg *d_msgs, size_t n_msgs, cons
         d_out_base == nullptr || d_workspace == nullptr)
         return fail(TDES_ERR_ARG, "NULL pointer");
     if (n_schedules == 0) return fail(TDES_ERR_ARG, "no schedules");
+    if (n_schedules > TDES_BATCH_MAX_SCHEDULES)
+        return fail(TDES_ERR_ARG, "%zu schedules: at most %u per batch", n_schedules,
+                    (unsigned)TDES_BATCH_MAX_SCHEDULES);
+    if (n_msgs > TDES_BATCH_MAX_MSGS)
+        return fail(TDES_ERR_ARG, "%zu messages: at most %u per batch", n_msgs,
+                    (unsigned)TDES_BATCH_MAX_MSGS);
     if (workspace_bytes < tdes::batch_workspace_bytes(n_msgs))
         return fail(TDES_ERR_ARG, "workspace too small (%zu < %zu bytes)", workspace_bytes,
                     tdes::batch_workspace_bytes(n_msgs));

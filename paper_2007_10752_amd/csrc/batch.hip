@@ -8,10 +8,13 @@
 // slices, one per lane, 64 consecutive slices per wave per step.  Each lane
 // finds its message (a 64-way search for the message of the wave's first
 // slice, then a shuffle search over the next 64 message starts), loads its
-// 256 bytes, and runs the same bitsliced core as the plain kernel, with its
-// message's key masks: two mask words per round read from the device
-// schedule table (cached; identical across lanes of one message) and
-// expanded bit by bit with v_bfe_i32.
+// 256 bytes, and runs the same bitsliced core as the plain kernel.  The key
+// masks: a wave's 64 slices lie in a run of consecutive messages; the wave
+// expands the masks of up to KMAX of them together, one round ahead, into a
+// table in LDS (one row per message and round, in the plain kernel's
+// layout), and each lane reads its own message's row with the plain
+// kernel's piped LDS reads.  A wave spanning more messages takes one pass
+// per group of KMAX.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -19,9 +22,13 @@
 
 #include "bitslice_core.h"
 #include "internal.h"
+#include "lds_masks.h"
 
 #ifndef TDES_BATCH_MIN_WAVES
-#define TDES_BATCH_MIN_WAVES 3
+#define TDES_BATCH_MIN_WAVES 4
+#endif
+#ifndef TDES_BATCH_KMAX
+#define TDES_BATCH_KMAX 8  // messages per wave pass whose masks share the LDS table
 #endif
 #ifndef TDES_BATCH_GRID_MULT
 #define TDES_BATCH_GRID_MULT 2  // launched waves per resident wave slot
@@ -135,128 +142,267 @@ __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg
     }
 }
 
-// Round masks expanded from a lane's own mask words.
-struct LaneMasks {
-    uint32_t lo, hi;  // 32 output-XOR mask bits, 16 second-use mask bits
-    __device__ __forceinline__ uint32_t operator()(int i) const {
-        return (uint32_t)__builtin_amdgcn_sbfe((int)(i < 32 ? lo : hi), i < 32 ? i : i - 32, 1);
+// Key masks of the messages a wave works on, expanded cooperatively into a
+// table in LDS one round ahead of use (in place of each lane expanding its
+// own 48 masks per round).  The wave's lanes hold consecutive slices, so a
+// wave spans a run of consecutive messages; up to KMAX of them (a group) are
+// handled per pass.  Table of one wave: 2 round buffers x KMAX rows x
+// kRowWords words; a row holds one message's 64 masks of one round in the
+// plain kernel's layout (box j at 8 j: output masks o[0..3], second-use
+// masks e[0..3]), padded so that the rows of different messages start on
+// different banks.  Per round and message the wave writes 64 words, one per
+// lane (two VALU operations each), and every lane reads its own message's
+// row with the piped LDS reads of the plain kernel.
+constexpr int kRowWords = 68;
+
+// The bit of a round's two key words (lo: output masks, hi: second uses) a
+// lane expands: entry l of a row is slot l % 8 of S-box l / 8, an output
+// mask (bit 4 j + q of lo) or a second-use mask (bit kBsBoxDup[4 j + i] of
+// hi, as bit 32 + k of the pair); entries no S-box reads get bit 0.
+__device__ __forceinline__ uint32_t row_entry_bit(int lane) {
+    const int j = lane >> 3, sl = lane & 7;
+    if (sl < 4) return (uint32_t)(4 * j + sl);
+    const int k = box_dup(j, sl - 4);
+    return k < 0 ? 0u : 32u + (uint32_t)k;
+}
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+template <int KMAX>
+struct TableRounds {
+    lds_u32 *wr;          // this wave's table + lane: where this lane writes
+    const lds_u32 *p0;    // this lane's row in round buffer 0 (buffer 1 follows)
+    const uint32_t *sched;
+    uint32_t woff;        // lanes 2j, 2j + 1: byte offset of message j's key words of round 0
+    uint32_t wcur;        // lanes 2j, 2j + 1: message j's two key words of the round to build
+    uint32_t sel;         // byte address (for ds_bpermute) of the lane holding this lane's word
+                          // of message 0 (+ 8 j for message j)
+    uint32_t bit;         // bit of that word this lane expands
+    uint32_t kg;          // messages in the group (uniform, 1..KMAX)
+    BsBoxMasks pm[8];
+
+    static constexpr int kBuf = KMAX * kRowWords;  // words per round buffer
+
+    __device__ __forceinline__ void fetch(int t) {
+        wcur = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(sched) +
+                                                   (woff + 8u * (uint32_t)t));
     }
-};
-struct LaneRounds {
-    const uint32_t *kw;  // this lane's 100 mask words (round t at 2t, 2t+1)
-    __device__ __forceinline__ uint2 load(int t) const {
-        return *reinterpret_cast<const uint2 *>(kw + 2 * t);
+    // message J's masks of the round whose words are in wcur, into buffer B.
+    // Every row is written, also those of messages past the group (lanes
+    // past 2 kg hold copies of the last message's words): the round body
+    // must stay free of branches, or the compiler hoists all eight S-boxes'
+    // mask reads to the top of the round loop and runs out of registers.
+    // (sl: sel, made opaque each round so that sel + 8 j is computed here
+    // and not hoisted out of the round loop, one register per message)
+    template <int B, int J0>
+    __device__ __forceinline__ void build_group(uint32_t sl) {
+        constexpr int N = KMAX - J0 < 4 ? KMAX - J0 : 4;  // four reads in flight at a time
+        uint32_t x[N];
+#pragma unroll
+        for (int i = 0; i < N; i++)
+            x[i] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(sl + 8u * (J0 + i)), (int)wcur);
+#pragma unroll
+        for (int i = 0; i < N; i++)
+            wr[B * kBuf + (J0 + i) * kRowWords] = (uint32_t)__builtin_amdgcn_sbfe((int)x[i], (int)bit, 1);
+        if constexpr (J0 + N < KMAX) build_group<B, J0 + N>(sl);
     }
-    __device__ __forceinline__ LaneMasks masks(uint2 w) const { return LaneMasks{w.x, w.y}; }
+    // the masks of round t (its words in wcur) into buffer B = t % 2
+    template <int B>
+    __device__ __forceinline__ void build() {
+        uint32_t sl = sel;
+        asm volatile("" : "+v"(sl));
+        build_group<B, 0>(sl);
+    }
+    __device__ __forceinline__ void start() {
+        fetch(0);
+        build<0>();
+        fetch(1);
+#pragma unroll
+        for (int j = 0; j < TDES_BS_PIPE; j++) LdsBoxLoad{}(pm[j], p0 + kBsBoxMasks * j, BS_BOX_NDUP[j]);
+    }
+    template <int PH>
+    __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
+        // round t + 1's masks go to the other buffer, whose last reads (round
+        // t - 1) were issued before: a wave's LDS operations run in order.
+        // After round 47 this builds an unused round from the extra words,
+        // into buffer 0, which the rounds no longer read.
+        build<PH ^ 1>();
+        fetch(t + 2);
+        bs_round_piped<TDES_BS_PIPE>(d, r, p0 + PH * kBuf, p0 + (PH ^ 1) * kBuf, pm, LdsBoxLoad{});
+    }
+    // XOR extra mask group g (word 96 + g of each message) into a: expanded
+    // into a buffer the rounds are not using (buffer 1 between passes,
+    // buffer 0 before the first round and after the last), then read 4
+    // masks at a time with the next 4 requested
+    __device__ __forceinline__ void extra(int g, uint32_t (&a)[32]) const {
+        typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
+        const int b = (g == kGroupRemask16 || g == kGroupRemask32) ? 1 : 0;
+        const uint32_t l = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        // lanes 2j, 2j + 1: word 96 + g of message j (woff is even-word aligned
+        // per lane pair, so both read the same word)
+        const uint32_t xw = *reinterpret_cast<const uint32_t *>(
+            reinterpret_cast<const char *>(sched) + ((woff & ~7u) + 4u * (96u + (uint32_t)g)));
+        // (every row, all 64 entries: only entries 0..31 of this lane's row
+        // are read)
+#pragma unroll
+        for (int j = 0; j < KMAX; j++) {
+            const uint32_t x = (uint32_t)__builtin_amdgcn_ds_bpermute(8 * j, (int)xw);
+            wr[b * kBuf + j * kRowWords] = (uint32_t)__builtin_amdgcn_sbfe((int)x, (int)(l & 31u), 1);
+        }
+        const lds_u32 *p = p0 + b * kBuf;
+        v4u m[2];
+        m[0] = *(lds_v4u *)p;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            if (q < 7) m[(q + 1) & 1] = *(lds_v4u *)(p + 4 * q + 4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; i++) a[4 * q + i] ^= m[q & 1][i];
+        }
+    }
 };
 
-// Round masks from words the whole wave shares (a wave inside one
-// message): scalar loads, scalar bit extraction, scalar VALU operands.
-struct WaveMasks {
-    uint32_t lo, hi;
-    __device__ __forceinline__ uint32_t operator()(int i) const {
-        const uint32_t w = i < 32 ? lo : hi;
-        return (uint32_t)(((int32_t)(w << (31 - (i < 32 ? i : i - 32)))) >> 31);
-    }
+// A lane's slice between the lookup and the cipher phases of a pass: kept in
+// LDS (volatile, so the compiler cannot forward it in registers), so that
+// nothing of the lookup stays in registers through the rounds.
+struct LaneSlice {
+    uint64_t src, dst;  // device addresses of the lane's 256-byte slice
+    uint32_t nb;        // bytes of it in the message (0: no work for this lane)
+    uint32_t row;       // this lane's row of the mask table
 };
-struct WaveRounds {
-    const uint32_t *kw;  // wave-uniform
-    __device__ __forceinline__ uint2 load(int t) const {
-        return *reinterpret_cast<const uint2 *>(kw + 2 * t);
-    }
-    __device__ __forceinline__ WaveMasks masks(uint2 w) const { return WaveMasks{w.x, w.y}; }
-};
+typedef __attribute__((address_space(3))) volatile uint64_t lds_vu64;
+typedef __attribute__((address_space(3))) volatile uint32_t lds_vu32;
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TDES_BATCH_MIN_WAVES, 8)))
-void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, size_t n_msgs,
-                           const uint32_t *__restrict__ sched, size_t n_sched, const uint8_t *in,
+template <int KMAX, int WAVES>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
+                           const uint32_t *__restrict__ sched, uint32_t n_sched, const uint8_t *in,
                            uint8_t *out, const uint64_t *__restrict__ ws) {
+    __shared__ __align__(16) uint32_t tables[kWavesPerBlock][2 * KMAX * kRowWords];
+    __shared__ LaneSlice slices[kWavesPerBlock][kWave];
     const uint64_t total = ws[0];
     const uint64_t *first = ws + kWsHeader;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const uint32_t lane = threadIdx.x % kWave;
+    LaneSlice *mine_ls = &slices[wave][lane];
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t base = ((uint64_t)blockIdx.x * kWavesPerBlock + wave) * kWave; base < total;
          base += stride) {
-        // Issue priority: the message lookup, loads and input transposes at
-        // the highest, the rounds at the lowest, so a wave that has just
-        // started reaches its rounds sooner (measured at a settled clock:
-        // 2 % faster).
-        __builtin_amdgcn_s_setprio(3);
-        // Message holding slice `base`: the largest m with first[m] <= base
-        // (first[] is non-decreasing, first[n_msgs] = total > base).  A
-        // 64-way search: each step every lane tests one evenly spaced entry
-        // and a ballot keeps the sub-range, so 16k messages take 3 steps.
-        size_t lo = 0, hi = n_msgs;  // first[lo] <= base < first[hi]
-        while (hi - lo > 1) {
-            const size_t step = (hi - lo + kWave - 1) / kWave;
-            const size_t idx = lo + (size_t)(lane + 1) * step;
-            const bool le = idx < hi && first[idx] <= base;
-            const size_t k = (size_t)__popcll(__ballot(le));  // tests passed: a prefix of lanes
-            const size_t nlo = lo + k * step, nhi = lo + (k + 1) * step;
-            lo = nlo;
-            hi = nhi < hi ? nhi : hi;
-        }
-        // Each lane's message: m0 plus the number of the next 64 message
-        // starts at or before its slice, found by a binary search over the
-        // starts held one per lane.  Past 63 of them (only with empty
-        // messages) the lane walks on.
-        const uint64_t s = base + lane;
-        const bool active = s < total;
-        const size_t nxt = lo + 1 + lane;
-        const uint64_t start_l = nxt <= n_msgs ? first[nxt] : ~0ull;
-        int r = 0;
+        // Passes over groups of KMAX consecutive messages of the wave: one
+        // pass unless the wave's 64 slices span more than KMAX messages.
+        uint32_t g0 = 0, n_wave_msgs = 1;
+        do {
+            // Issue priority: the message lookup, loads and input transposes
+            // at the highest, the rounds at the lowest, so a wave that has
+            // just started reaches its rounds sooner.
+            __builtin_amdgcn_s_setprio(3);
+            uint32_t lo, woff;
+            {
+                // Message holding slice `base`: the largest m with first[m]
+                // <= base (first[] is non-decreasing, first[n_msgs] = total >
+                // base).  A 64-way search: each step every lane tests one
+                // evenly spaced entry and a ballot keeps the sub-range, so
+                // 16k messages take 3 steps.
+                lo = 0;
+                uint32_t hi = n_msgs;  // first[lo] <= base < first[hi]
+                while (hi - lo > 1) {
+                    const uint32_t step = (hi - lo + kWave - 1) / kWave;
+                    const uint64_t idx = lo + (uint64_t)(lane + 1) * step;
+                    const bool le = idx < hi && first[idx] <= base;
+                    const uint32_t k = (uint32_t)__popcll(__ballot(le));  // a prefix of lanes
+                    const uint64_t nhi = lo + (uint64_t)(k + 1) * step;
+                    lo = lo + k * step;
+                    hi = nhi < hi ? (uint32_t)nhi : hi;
+                }
+                lo = __builtin_amdgcn_readfirstlane(lo);
+                // Each lane's message: m0 plus the number of the next 64
+                // message starts at or before its slice, found by a binary
+                // search over the starts held one per lane.  Past 63 of them
+                // (only with empty messages) the lane walks on.
+                const uint64_t s = base + lane;
+                const bool active = s < total;
+                const uint32_t nxt = lo + 1 + lane;
+                const uint64_t start_l = nxt <= n_msgs ? first[nxt] : ~0ull;
+                int r = 0;
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const uint64_t b = __shfl(start_l, r + step - 1);
-            if (b <= s) r += step;
-        }
-        // (a lane past the end keeps m0: its count may include first[n_msgs])
-        size_t m = active ? lo + (size_t)r : lo;
-        if (active)
-            while (first[m + 1] <= s) m++;
-        const tdes_msg d = msgs[m];
-        const uint64_t off = (s - first[m]) * kSlice;
-        const uint32_t nb = active ? (uint32_t)min((uint64_t)kSlice, d.nbytes - off) : 0u;
-        const uint8_t *src = in + d.in_off + off;
-        uint8_t *dst = out + d.out_off + off;
-        const uint32_t sidx = d.sched_idx < n_sched ? d.sched_idx : 0u;
-        const uint32_t *kw = sched + (size_t)sidx * kDeviceScheduleWords + (d.dir & 1u) * kDirWords;
-
-        uint32_t h0[32], h1[32];
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const uint64_t b = __shfl(start_l, r + step - 1);
+                    if (b <= s) r += step;
+                }
+                // (a lane past the end keeps m0: its count may include first[n_msgs])
+                uint32_t m = active ? lo + (uint32_t)r : lo;
+                if (active)
+                    while (first[m + 1] <= s) m++;
+                // The wave's messages lo .. m_hi (lane 0 holds the first, the
+                // last active lane the last); this lane's is number m - lo.
+                const uint64_t left = total - base;
+                const int last = left > (uint64_t)kWave ? kWave - 1 : (int)left - 1;
+                n_wave_msgs = (uint32_t)__builtin_amdgcn_readlane((int)m, last) - lo + 1;
+                const uint32_t slot = m - lo;
+                const bool mine = active && slot - g0 < (uint32_t)KMAX;
+                const tdes_msg d = msgs[m];
+                const uint64_t off = (s - first[m]) * kSlice;
+                *(lds_vu64 *)&mine_ls->src = (uint64_t)(uintptr_t)(in + d.in_off + off);
+                *(lds_vu64 *)&mine_ls->dst = (uint64_t)(uintptr_t)(out + d.out_off + off);
+                *(lds_vu32 *)&mine_ls->nb = mine ? (uint32_t)min((uint64_t)kSlice, d.nbytes - off) : 0u;
+                *(lds_vu32 *)&mine_ls->row = (slot - g0) % KMAX;  // (any row for other groups)
+                // lanes 2j, 2j + 1: the two key words of round 0 of the
+                // group's message j (the last one for lanes past the group)
+                const uint32_t kg = min(n_wave_msgs - g0, (uint32_t)KMAX);
+                const tdes_msg dj = msgs[lo + g0 + min(lane >> 1, kg - 1)];
+                woff = 4u * ((dj.sched_idx < n_sched ? dj.sched_idx : 0u) *
+                                 (uint32_t)kDeviceScheduleWords +
+                             (dj.dir & 1u) * (uint32_t)kDirWords + (lane & 1u));
+                if (__ballot(mine) == 0) continue;  // a group of empty messages
+            }
+            uint32_t h0[32], h1[32];
+            {
+                const uint8_t *src = (const uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->src;
+                const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
 #pragma unroll
-        for (int k = 0; k < 32; k++) {
-            uint2 v = make_uint2(0u, 0u);
-            if ((uint32_t)k * 8u < nb) v = *reinterpret_cast<const uint2 *>(src + 8 * k);
-            h0[k] = v.x;
-            h1[k] = v.y;
-        }
-        transpose32(h0);
-        transpose32(h1);
-        // lane 0's schedule, addressed from the kernel argument so the
-        // compiler may read it with scalar loads
-        const uint32_t s0 = __builtin_amdgcn_readfirstlane(sidx);
-        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d.dir & 1u);
-        const uint32_t *kw0 = sched + (size_t)s0 * kDeviceScheduleWords + d0 * kDirWords;
-        __builtin_amdgcn_s_setprio(0);
-        if (__all(active && sidx == s0 && (d.dir & 1u) == d0)) {
-            // every lane works on the same message and direction
-            auto rr = prefetch_rounds(WaveRounds{kw0}, [kw0](int g, int i) {
-                return (uint32_t)(((int32_t)(kw0[96 + g] << (31 - i))) >> 31);
-            });
+                for (int k = 0; k < 32; k++) {
+                    uint2 v = make_uint2(0u, 0u);
+                    if ((uint32_t)k * 8u < nb) v = *reinterpret_cast<const uint2 *>(src + 8 * k);
+                    h0[k] = v.x;
+                    h1[k] = v.y;
+                }
+            }
+            TableRounds<KMAX> rr;
+            rr.kg = min(n_wave_msgs - g0, (uint32_t)KMAX);
+            rr.sched = sched;
+            rr.woff = woff;
+            {
+                // entry `lane` of a row: bit eb of the round's word pair (lo,
+                // hi as bits 32..63), found in lane 2j (lo) or 2j + 1 (hi)
+                const uint32_t eb = row_entry_bit((int)lane);
+                rr.sel = 4u * (eb >> 5);
+                rr.bit = eb & 31u;
+            }
+            rr.wr = (lds_u32 *)tables[wave] + lane;
+            rr.p0 = (const lds_u32 *)tables[wave] + *(lds_vu32 *)&mine_ls->row * kRowWords;
+            transpose32(h0);
+            __builtin_amdgcn_sched_barrier(0);
+            transpose32(h1);
+            pin_words(h0);
+            pin_words(h1);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(0);
             des3_planes(h0, h1, rr);
-        } else {
-            auto rr = prefetch_rounds(LaneRounds{kw}, [kw](int g, int i) {
-                return (uint32_t)__builtin_amdgcn_sbfe((int)kw[96 + g], i, 1);
-            });
-            des3_planes(h0, h1, rr);
-        }
-        transpose32(h0);
-        transpose32(h1);
+            __builtin_amdgcn_sched_barrier(0);
+            transpose32(h0);
+            __builtin_amdgcn_sched_barrier(0);
+            transpose32(h1);
+            pin_words(h0);
+            pin_words(h1);
+            {
+                uint8_t *dst = (uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->dst;
+                const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
 #pragma unroll
-        for (int k = 0; k < 32; k++)
-            if ((uint32_t)k * 8u < nb)
-                *reinterpret_cast<uint2 *>(dst + 8 * k) = make_uint2(h0[k], h1[k]);
+                for (int k = 0; k < 32; k++)
+                    if ((uint32_t)k * 8u < nb)
+                        *reinterpret_cast<uint2 *>(dst + 8 * k) = make_uint2(h0[k], h1[k]);
+            }
+        } while ((g0 += KMAX) < n_wave_msgs);
     }
 }
 
@@ -329,8 +475,8 @@ hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, h
 hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                                  size_t n_schedules, const uint8_t *in, uint8_t *out,
                                  const uint64_t *ws, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
-                       msgs, n_msgs, schedules, n_schedules, in, out, ws);
+    hipLaunchKernelGGL((batch_bitslice_kernel<TDES_BATCH_KMAX, TDES_BATCH_MIN_WAVES>), dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
+                       msgs, (uint32_t)n_msgs, schedules, (uint32_t)n_schedules, in, out, ws);
     return hipGetLastError();
 }
 
@@ -379,8 +525,8 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                        n_schedules, BatchBounds{in_bytes, out_bytes}, ws, skipped_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_bitslice_kernel, dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
-                       msgs, n_msgs, schedules, n_schedules, in, out, ws);
+    hipLaunchKernelGGL((batch_bitslice_kernel<TDES_BATCH_KMAX, TDES_BATCH_MIN_WAVES>), dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
+                       msgs, (uint32_t)n_msgs, schedules, (uint32_t)n_schedules, in, out, ws);
     return hipGetLastError();
 }
 

@@ -67,6 +67,14 @@ __device__ __forceinline__ void swap_stage(uint32_t (&x)[32]) {
     }
 }
 
+// Makes the 32 words exist here: pure operations that produce them cannot
+// be sunk past this point into later blocks (where the operands they need
+// would stay live, costing registers).  No instruction is emitted.
+__device__ __forceinline__ void pin_words(uint32_t (&x)[32]) {
+#pragma unroll
+    for (int i = 0; i < 32; i++) asm volatile("" : "+v"(x[i]));
+}
+
 // Exact transpose: afterwards bit b of x[p] is the old bit p of x[b].
 __device__ __forceinline__ void transpose32(uint32_t (&x)[32]) {
     swap_stage<16>(x);

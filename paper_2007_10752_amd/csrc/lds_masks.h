@@ -26,7 +26,8 @@ struct LdsBoxLoad {
     // n (0, 2 or 4) is a compile-time constant after inlining; only words that
     // are used are read, so no read's destination register is reused while
     // the read is in flight
-    __device__ __forceinline__ void operator()(BsBoxMasks &m, const uint32_t *p, int n) const {
+    template <class P>
+    __device__ __forceinline__ void operator()(BsBoxMasks &m, P p, int n) const {
         // volatile keeps each read where it is issued (otherwise the reads
         // that cross the loop back edge are folded into reads at first use)
         typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
@@ -53,7 +54,8 @@ struct LdsPipedRounds {
     }
     template <int PH>
     __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
-        bs_round_piped<TDES_BS_PIPE>(d, r, km + kBsRoundMasks * t, pm, LdsBoxLoad{});
+        bs_round_piped<TDES_BS_PIPE>(d, r, km + kBsRoundMasks * t, km + kBsRoundMasks * (t + 1), pm,
+                                     LdsBoxLoad{});
     }
     // XOR extra group g into a, 4 masks at a time with the next 4 already
     // requested (32 masks in flight at once would need 32 more registers)

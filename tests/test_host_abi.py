@@ -175,6 +175,10 @@ def test_batch_submit_argument_errors():
     assert call(ws_bytes=8) == -1
     assert b"workspace too small" in lib.tdes_last_error()
     assert call(n_sched=0) == -1
+    assert call(n_sched=(1 << 22) + 1) == -1
+    assert b"schedules: at most" in lib.tdes_last_error()
+    assert call(n=(1 << 31) + 1, ws_bytes=1 << 40) == -1
+    assert b"messages: at most" in lib.tdes_last_error()
     assert call(sched=0x1008) == -3     # schedules must be 16-byte aligned
     assert call(d_in=0x100004) == -3
     assert call(msgs=0) == -1

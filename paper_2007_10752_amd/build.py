@@ -33,21 +33,31 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose=False):
+def build(verbose=False, sanitize=None):
+    """Build the library.  sanitize (e.g. "address,undefined" or "thread")
+    instruments the host code only, for CPU test runs, and writes
+    _build/<name>/libtdes.so instead of the package's library; device code
+    is compiled as usual."""
     from .gen import emit
     emit.main() if verbose else _quiet(emit.main)
-    os.makedirs(BUILD_DIR, exist_ok=True)
+    out_dir = BUILD_DIR if not sanitize else \
+        os.path.join(BUILD_DIR, "san_" + sanitize.replace(",", "_"))
+    lib = LIB if not sanitize else os.path.join(out_dir, "libtdes.so")
+    os.makedirs(out_dir, exist_ok=True)
+    # -Xarch_host: the sanitizer applies to host code, never to GPU code
+    san = ["-Xarch_host", "-fsanitize=" + sanitize, "-Xarch_host", "-fno-omit-frame-pointer",
+           "-Xarch_host", "-g"] if sanitize else []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD_DIR, src + ".o")
-        cmd = [HIPCC] + COMMON + (DEVICE if src.endswith(".hip") else []) + \
+        obj = os.path.join(out_dir, src + ".o")
+        cmd = [HIPCC] + COMMON + san + (DEVICE if src.endswith(".hip") else []) + \
               ["-c", os.path.join(CSRC, src), "-o", obj]
         _run(cmd, verbose)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + san + objs, verbose)
+    os.replace(tmp, lib)
+    return lib
 
 
 def _quiet(fn):

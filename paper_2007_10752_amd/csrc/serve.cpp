@@ -180,7 +180,7 @@ void reject(tdes_server *s, const tdes_request &r, double t, int32_t status) {
 
 // Admit the head of the queue if it fits: reserve its output and budget.
 bool admit_head(tdes_server *s, Active *a) {
-    const tdes_request &r = s->queue.front().first;
+    const tdes_request r = s->queue.front().first;  // a copy: the entry is popped below
     const uint64_t out_bytes = round_up(r.nbytes);
     if (s->st.in_flight_bytes + r.nbytes + out_bytes > s->budget) return false;
     uint64_t off;

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define TDES_ABI_VERSION 2
+#define TDES_ABI_VERSION 3
 
 typedef enum {
     TDES_OK = 0,
@@ -244,24 +244,70 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
 tdes_status tdes_ecb_host(const tdes_schedule *ks, int dir, const void *h_in, void *h_out,
                           size_t nbytes, void *d_work, size_t work_bytes, size_t chunk_bytes);
 
+/* Configuration of the batched kernel: which compiled variant runs and on
+ * how large a grid.  None of it changes results, only speed. */
+typedef struct {
+    uint32_t kmax;      /* messages per wave pass whose key masks share one LDS
+                           table (4, 8 or 16; a wave over more messages takes
+                           one pass per group)                              */
+    uint32_t waves;     /* waves per SIMD the variant's register budget is
+                           set for (3 or 4)                                 */
+    uint32_t grid_mult; /* grid = grid_mult x the workgroups that fit at
+                           once (1..4)                                      */
+    uint32_t saved;     /* output of tdes_batch_autotune: 1 if the result was
+                           written to the tuning cache; ignored on input    */
+} tdes_batch_config;
+
+/* The configuration batched calls use on the current device.  Until it is
+ * set (tdes_batch_set_config, tdes_batch_autotune) it is, from the first
+ * batched call on, the tuning cache's entry for this kind of device (same
+ * architecture name and compute-unit count), else the default
+ * {8, 4, 2}.  The tuning cache is the JSON file named by TDES_TUNE_CACHE
+ * (empty: no cache), else $XDG_CACHE_HOME/tdes/batch_tune.json, else
+ * ~/.cache/tdes/batch_tune.json.  Errors: TDES_ERR_ARG (NULL),
+ * TDES_ERR_DEVICE (no device). */
+tdes_status tdes_batch_get_config(tdes_batch_config *out);
+
+/* Set the configuration for later batched calls on the current device (the
+ * request server's batches included).  Errors: TDES_ERR_ARG (NULL, or not
+ * a compiled variant, or grid_mult outside 1..4), TDES_ERR_DEVICE. */
+tdes_status tdes_batch_set_config(const tdes_batch_config *cfg);
+
 /* Autotuner for the batched form: runs this batch (arguments and checks as
- * for tdes_batch_submit) at grids of 1, 2, 3 and 4 times the workgroups
- * that fit on the GPU at once, reps (>= 1) times each after one warm run,
- * timed with HIP events on `stream`.  The fastest grid is kept for every
- * later tdes_batch_submit on the current device (and the request server's
- * batches); its multiplier is written to *grid_multiplier.  Synchronous.
- * Every trial reads the input and writes the output, so the input range
- * [d_in_base, d_in_base + in_bytes) must not overlap the output range
- * (TDES_ERR_OVERLAP otherwise, in-place batches included): each trial then
- * writes the same result.  Batched calls from other threads on the same
- * device while it runs use the grid under trial (same results, other
- * speed).  Errors: those of tdes_batch_submit, TDES_ERR_OVERLAP, and
- * TDES_ERR_ARG for reps < 1 or a NULL grid_multiplier. */
+ * for tdes_batch_submit) in every configuration (each compiled variant at
+ * grids of 1, 2, 3 and 4 times the workgroups that fit at once), reps
+ * (>= 1) times each after one warm run, timed with HIP events on
+ * `stream`.  The fastest is kept for every later batched call on the
+ * current device (the request server's batches included), written to the
+ * tuning cache under this device kind (best->saved says whether it was),
+ * and returned in *best.  Synchronous.  Every trial reads the input and
+ * writes the output, so the input range [d_in_base, d_in_base + in_bytes)
+ * must not overlap the output range (TDES_ERR_OVERLAP otherwise, in-place
+ * batches included): each trial then writes the same result.  Batched
+ * calls from other threads on the same device while it runs use the
+ * configuration under trial (same results, other speed).  Errors: those of
+ * tdes_batch_submit, TDES_ERR_OVERLAP, and TDES_ERR_ARG for reps < 1 or a
+ * NULL best. */
 tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
                                 size_t n_schedules, const void *d_in_base, size_t in_bytes,
                                 void *d_out_base, size_t out_bytes, void *d_workspace,
                                 size_t workspace_bytes, void *stream, int reps,
-                                int *grid_multiplier);
+                                tdes_batch_config *best);
+
+/* The tuning cache file itself (host only, no device needed).  Load: the
+ * entry for `device` (an architecture name such as "gfx950:sramecc+:xnack-")
+ * and `cus` compute units from the JSON file at path into *out; returns 1
+ * if found and valid, 0 if the file or the entry is missing or unreadable,
+ * a negative tdes_status for bad arguments.  Save: write or replace that
+ * entry (us_per_batch is recorded beside it), keeping the file's other
+ * entries; the file is replaced atomically and its directory created.
+ * Errors: TDES_ERR_ARG (NULL or empty path, a device name with quotes,
+ * backslashes or control characters, an invalid configuration),
+ * TDES_ERR_DEVICE (the file could not be written). */
+int tdes_batch_config_load(const char *path, const char *device, uint32_t cus,
+                           tdes_batch_config *out);
+tdes_status tdes_batch_config_save(const char *path, const char *device, uint32_t cus,
+                                   const tdes_batch_config *cfg, double us_per_batch);
 
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
  * TDES_KERNEL_SPBOX; AUTO means the kernel AUTO selects) would receive for

@@ -117,6 +117,14 @@ tdes_status tdes_server_progress(tdes_server *s, tdes_completion *out, size_t ca
  * Errors: TDES_ERR_ARG if d_out is not a live result. */
 tdes_status tdes_server_release(tdes_server *s, void *d_out);
 
+/* tdes_server_release for n results at once (d_outs: n host-memory entries).
+ * Every live entry is released, whatever the others are; *n_released (if
+ * not NULL) receives how many were.  Errors: TDES_ERR_ARG for a NULL
+ * argument or if any entry is not a live result (the message names the
+ * first such entry). */
+tdes_status tdes_server_release_many(tdes_server *s, void *const *d_outs, size_t n,
+                                     size_t *n_released);
+
 tdes_status tdes_server_get_stats(const tdes_server *s, tdes_server_stats *out);
 
 /* The clock the completion times use (seconds, monotonic). */

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtdes.so")
-SOURCES = ("api.cpp", "keysched.cpp", "serve.cpp", "host_path.cpp", "bitslice.hip", "batch.hip",
+SOURCES = ("api.cpp", "keysched.cpp", "serve.cpp", "host_path.cpp", "batch_tune.cpp",
+           "bitslice.hip", "batch.hip",
            "spbox.hip", "probe.hip", "replica.hip")
 ARCH = os.environ.get("TDES_OFFLOAD_ARCH", "gfx950")
 

@@ -36,13 +36,12 @@ tdes_status check_buffers(const void *in, const void *out, size_t nbytes) {
     return TDES_OK;
 }
 
-// Checks shared by the batched calls (n_msgs > 0).
-tdes_status tdes_batch_submit_checks(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
-                                     size_t n_schedules, const void *d_in_base,
-                                     const void *d_out_base, const void *d_workspace,
-                                     size_t workspace_bytes) {
+// Checks shared by the batched calls (n_msgs > 0), on everything but the
+// workspace.
+tdes_status batch_checks(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                         size_t n_schedules, const void *d_in_base, const void *d_out_base) {
     if (d_msgs == nullptr || d_schedules == nullptr || d_in_base == nullptr ||
-        d_out_base == nullptr || d_workspace == nullptr)
+        d_out_base == nullptr)
         return fail(TDES_ERR_ARG, "NULL pointer");
     if (n_schedules == 0) return fail(TDES_ERR_ARG, "no schedules");
     if (n_schedules > TDES_BATCH_MAX_SCHEDULES)
@@ -51,12 +50,24 @@ tdes_status tdes_batch_submit_checks(const tdes_msg *d_msgs, size_t n_msgs, cons
     if (n_msgs > TDES_BATCH_MAX_MSGS)
         return fail(TDES_ERR_ARG, "%zu messages: at most %u per batch", n_msgs,
                     (unsigned)TDES_BATCH_MAX_MSGS);
+    if (((uintptr_t)d_msgs | (uintptr_t)d_in_base | (uintptr_t)d_out_base) % 8 != 0 ||
+        (uintptr_t)d_schedules % 16 != 0)
+        return fail(TDES_ERR_ALIGN, "misaligned pointer");
+    return TDES_OK;
+}
+
+// The checks above plus the caller's workspace.
+tdes_status tdes_batch_submit_checks(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
+                                     size_t n_schedules, const void *d_in_base,
+                                     const void *d_out_base, const void *d_workspace,
+                                     size_t workspace_bytes) {
+    if (d_workspace == nullptr) return fail(TDES_ERR_ARG, "NULL pointer");
+    tdes_status st = batch_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base, d_out_base);
+    if (st != TDES_OK) return st;
     if (workspace_bytes < tdes::batch_workspace_bytes(n_msgs))
         return fail(TDES_ERR_ARG, "workspace too small (%zu < %zu bytes)", workspace_bytes,
                     tdes::batch_workspace_bytes(n_msgs));
-    if (((uintptr_t)d_msgs | (uintptr_t)d_in_base | (uintptr_t)d_out_base |
-         (uintptr_t)d_workspace) % 8 != 0 || (uintptr_t)d_schedules % 16 != 0)
-        return fail(TDES_ERR_ALIGN, "misaligned pointer");
+    if ((uintptr_t)d_workspace % 8 != 0) return fail(TDES_ERR_ALIGN, "misaligned pointer");
     return TDES_OK;
 }
 
@@ -267,10 +278,9 @@ tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const voi
                                 size_t n_schedules, const void *d_in_base, size_t in_bytes,
                                 void *d_out_base, size_t out_bytes, void *d_workspace,
                                 size_t workspace_bytes, void *stream, int reps,
-                                int *grid_multiplier) {
+                                tdes_batch_config *best) {
     g_last_error.clear();
-    if (reps < 1 || grid_multiplier == nullptr)
-        return fail(TDES_ERR_ARG, "reps must be >= 1 and grid_multiplier non-NULL");
+    if (reps < 1 || best == nullptr) return fail(TDES_ERR_ARG, "reps must be >= 1 and best non-NULL");
     if (n_msgs == 0) return fail(TDES_ERR_ARG, "nothing to tune on: no messages");
     // same checks as tdes_batch_submit
     tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
@@ -282,12 +292,80 @@ tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const voi
     if (in_bytes > 0 && out_bytes > 0 && a < b + out_bytes && b < a + in_bytes)
         return fail(TDES_ERR_OVERLAP,
                     "autotuning runs the batch several times: input and output must not overlap");
+    tdes::BatchConfig c;
+    float us = 0;
     hipError_t e = tdes::batch_autotune(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
                                         n_schedules, static_cast<const uint8_t *>(d_in_base),
                                         in_bytes, static_cast<uint8_t *>(d_out_base), out_bytes,
                                         static_cast<uint64_t *>(d_workspace),
-                                        static_cast<hipStream_t>(stream), reps, grid_multiplier);
+                                        static_cast<hipStream_t>(stream), reps, &c, &us);
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "autotune failed: %s", hipGetErrorString(e));
+    best->kmax = (uint32_t)c.kmax;
+    best->waves = (uint32_t)c.waves;
+    best->grid_mult = (uint32_t)c.grid_mult;
+    best->saved = (!tdes::tune_cache_path().empty() && tdes::batch_config_persist(c, us)) ? 1u : 0u;
+    return TDES_OK;
+}
+
+tdes_status tdes_batch_get_config(tdes_batch_config *out) {
+    g_last_error.clear();
+    if (out == nullptr) return fail(TDES_ERR_ARG, "NULL config");
+    tdes::BatchConfig c;
+    hipError_t e = tdes::batch_config_current(&c);
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "no device: %s", hipGetErrorString(e));
+    out->kmax = (uint32_t)c.kmax;
+    out->waves = (uint32_t)c.waves;
+    out->grid_mult = (uint32_t)c.grid_mult;
+    out->saved = 0;
+    return TDES_OK;
+}
+
+namespace {
+bool to_config(const tdes_batch_config *cfg, tdes::BatchConfig *c) {
+    if (cfg == nullptr || cfg->kmax > 64 || cfg->waves > 64 || cfg->grid_mult > 64) return false;
+    *c = tdes::BatchConfig{(int)cfg->kmax, (int)cfg->waves, (int)cfg->grid_mult};
+    return tdes::batch_config_valid(*c);
+}
+}  // namespace
+
+tdes_status tdes_batch_set_config(const tdes_batch_config *cfg) {
+    g_last_error.clear();
+    tdes::BatchConfig c;
+    if (!to_config(cfg, &c)) return fail(TDES_ERR_ARG, "not a compiled batched-kernel configuration");
+    hipError_t e = tdes::batch_config_set(c);
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "no device: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
+int tdes_batch_config_load(const char *path, const char *device, uint32_t cus,
+                           tdes_batch_config *out) {
+    g_last_error.clear();
+    if (path == nullptr || *path == '\0' || device == nullptr || out == nullptr)
+        return fail(TDES_ERR_ARG, "NULL or empty argument");
+    tdes::BatchConfig c;
+    const int r = tdes::cache_load(path, device, (long)cus, &c);
+    if (r < 0) return fail(TDES_ERR_ARG, "bad device name");
+    if (r == 1) {
+        out->kmax = (uint32_t)c.kmax;
+        out->waves = (uint32_t)c.waves;
+        out->grid_mult = (uint32_t)c.grid_mult;
+        out->saved = 0;
+    }
+    return r;
+}
+
+tdes_status tdes_batch_config_save(const char *path, const char *device, uint32_t cus,
+                                   const tdes_batch_config *cfg, double us_per_batch) {
+    g_last_error.clear();
+    tdes::BatchConfig c;
+    if (path == nullptr || *path == '\0' || device == nullptr || !to_config(cfg, &c))
+        return fail(TDES_ERR_ARG, "NULL or empty argument, or not a compiled configuration");
+    if (strchr(device, '"') || strchr(device, '\\') || *device == '\0')
+        return fail(TDES_ERR_ARG, "bad device name");
+    for (const char *p = device; *p; p++)
+        if ((unsigned char)*p < 0x20) return fail(TDES_ERR_ARG, "bad device name");
+    if (!tdes::cache_save(path, device, (long)cus, c, us_per_batch))
+        return fail(TDES_ERR_DEVICE, "could not write %s", path);
     return TDES_OK;
 }
 

@@ -24,15 +24,12 @@
 #include "internal.h"
 #include "lds_masks.h"
 
-#ifndef TDES_BATCH_MIN_WAVES
-#define TDES_BATCH_MIN_WAVES 4
-#endif
-#ifndef TDES_BATCH_KMAX
-#define TDES_BATCH_KMAX 8  // messages per wave pass whose masks share the LDS table
-#endif
-#ifndef TDES_BATCH_GRID_MULT
-#define TDES_BATCH_GRID_MULT 2  // launched waves per resident wave slot
-#endif
+// The compiled variants of the batched cipher, X(KMAX, WAVES): KMAX
+// messages per wave pass share the LDS mask table; WAVES waves per SIMD is
+// the occupancy the register budget is set for.  The first is the default
+// (with a grid of twice the resident workgroups); tdes_batch_autotune picks
+// among all of them and grids of 1..4 times the resident workgroups.
+#define TDES_BATCH_VARIANTS(X) X(8, 4) X(4, 4) X(16, 4) X(8, 3) X(4, 3) X(16, 3)
 
 namespace tdes {
 
@@ -421,48 +418,90 @@ __global__ __launch_bounds__(256) void expand_kernel(const uint8_t *keys24, size
     bitslice_mask_words(k, dir, schedules + b * kDeviceScheduleWords + dir * kDirWords);
 }
 
-// The batched kernel's grid: TDES_BATCH_GRID_MULT times the workgroups that
-// fit at once.  Each wave strides over the 64-slice groups, so any grid is
+// The batched kernel's grid: grid_mult times the workgroups that fit at
+// once.  Each wave strides over the 64-slice groups, so any grid is
 // correct; launching more waves than fit lets the hardware start a new wave
 // wherever one finishes, so the last groups of a batch are spread over the
 // whole GPU instead of being left to the persistent waves' final pass (a
 // wave with no group left exits at once).
-//
-// The multiplier is TDES_BATCH_GRID_MULT unless tdes_batch_autotune has
-// measured a better one for the current device.
 constexpr int kMaxDevices = 64;
 constexpr int kMaxGridMult = 4;
-std::atomic<int> g_tuned_mult[kMaxDevices];  // 0: not tuned
+constexpr BatchConfig kDefaultConfig{8, 4, 2};
 
 int current_device() {
     int dev = 0;
     return hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices ? dev : 0;
 }
 
-// Workgroups of the batched kernel that fit on the current device at once,
-// cached per device.
-std::atomic<int> g_resident[kMaxDevices];
-
+// Workgroups of variant <K, W> that fit on the current device at once
+// (occupancy calculator: registers and LDS), cached per device.
+template <int K, int W>
 int resident_blocks() {
+    static std::atomic<int> cache[kMaxDevices];
     const int dev = current_device();
-    int v = g_resident[dev].load();
+    int v = cache[dev].load();
     if (v == 0) {
-        int cus = 0;
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_bitslice_kernel<K, W>,
+                                                         kThreads, 0) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = W;  // 4 SIMDs x W waves, 4 waves per workgroup
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
-        v = cus * 4 * TDES_BATCH_MIN_WAVES / kWavesPerBlock;  // 4 SIMDs per CU
-        g_resident[dev].store(v);
+        v = per_cu * cus;
+        cache[dev].store(v);
     }
     return v;
 }
 
-int batch_grid_blocks() {
-    const int m = g_tuned_mult[current_device()].load();
-    return resident_blocks() * (m > 0 ? m : TDES_BATCH_GRID_MULT);
+template <int K, int W>
+hipError_t launch_cipher_variant(int grid_mult, const tdes_msg *msgs, uint32_t n_msgs,
+                                 const uint32_t *sched, uint32_t n_sched, const uint8_t *in,
+                                 uint8_t *out, const uint64_t *ws, hipStream_t stream) {
+    hipLaunchKernelGGL((batch_bitslice_kernel<K, W>), dim3(resident_blocks<K, W>() * grid_mult),
+                       dim3(kThreads), 0, stream, msgs, n_msgs, sched, n_sched, in, out, ws);
+    return hipGetLastError();
+}
+
+// The batched cipher in the current device's configuration.
+hipError_t launch_cipher(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sched,
+                         size_t n_sched, const uint8_t *in, uint8_t *out, const uint64_t *ws,
+                         hipStream_t stream) {
+    BatchConfig c;
+    const hipError_t e = batch_config_current(&c);
+    if (e != hipSuccess) return e;
+#define TDES_LAUNCH_IF(K, W)                                                                   \
+    if (c.kmax == K && c.waves == W)                                                           \
+        return launch_cipher_variant<K, W>(c.grid_mult, msgs, (uint32_t)n_msgs, sched,          \
+                                           (uint32_t)n_sched, in, out, ws, stream);
+    TDES_BATCH_VARIANTS(TDES_LAUNCH_IF)
+#undef TDES_LAUNCH_IF
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
+
+bool batch_config_valid(const BatchConfig &c) {
+    if (c.grid_mult < 1 || c.grid_mult > kMaxGridMult) return false;
+#define TDES_VALID_IF(K, W) \
+    if (c.kmax == K && c.waves == W) return true;
+    TDES_BATCH_VARIANTS(TDES_VALID_IF)
+#undef TDES_VALID_IF
+    return false;
+}
+
+BatchConfig batch_config_default() { return kDefaultConfig; }
+
+int batch_config_list(BatchConfig *out, int cap) {
+    int n = 0;
+#define TDES_LIST(K, W)                                                                   \
+    for (int m = 1; m <= kMaxGridMult; m++, n++)                                          \
+        if (n < cap) out[n] = BatchConfig{K, W, m};
+    TDES_BATCH_VARIANTS(TDES_LIST)
+#undef TDES_LIST
+    return n;
+}
 
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream) {
     const size_t threads = 2 * n, blocks = (threads + 255) / 256;
@@ -475,43 +514,48 @@ hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, h
 hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                                  size_t n_schedules, const uint8_t *in, uint8_t *out,
                                  const uint64_t *ws, hipStream_t stream) {
-    hipLaunchKernelGGL((batch_bitslice_kernel<TDES_BATCH_KMAX, TDES_BATCH_MIN_WAVES>), dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
-                       msgs, (uint32_t)n_msgs, schedules, (uint32_t)n_schedules, in, out, ws);
-    return hipGetLastError();
+    return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);
 }
 
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                           size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
                           uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
-                          int *mult_out) {
-    const int dev = current_device();
+                          BatchConfig *best_out, float *best_us) {
+    BatchConfig keep;
+    hipError_t e = batch_config_current(&keep);
+    if (e != hipSuccess) return e;
+    BatchConfig cands[64];
+    const int n_cands = batch_config_list(cands, 64);
     hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
+    e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     float best_ms = 0;
-    int best = TDES_BATCH_GRID_MULT;
+    BatchConfig best = keep;
     auto run = [&]() {
         return launch_batch(msgs, n_msgs, schedules, n_schedules, in, in_bytes, out, out_bytes, ws,
                             nullptr, stream);
     };
-    for (int m = 1; m <= kMaxGridMult && e == hipSuccess; m++) {
-        g_tuned_mult[dev].store(m);
-        e = run();  // warm
+    for (int i = 0; i < n_cands && e == hipSuccess; i++) {
+        e = batch_config_set(cands[i]);
+        if (e == hipSuccess) e = run();  // warm
         if (e == hipSuccess) e = hipEventRecord(a, stream);
         for (int r = 0; r < reps && e == hipSuccess; r++) e = run();
         if (e == hipSuccess) e = hipEventRecord(b, stream);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess && (m == 1 || ms < best_ms)) {
+        if (e == hipSuccess && (i == 0 || ms < best_ms)) {
             best_ms = ms;
-            best = m;
+            best = cands[i];
         }
     }
-    g_tuned_mult[dev].store(e == hipSuccess ? best : 0);
+    (void)batch_config_set(e == hipSuccess ? best : keep);
     if (a != nullptr) (void)hipEventDestroy(a);
     if (b != nullptr) (void)hipEventDestroy(b);
-    if (e == hipSuccess) *mult_out = best;
+    if (e == hipSuccess) {
+        *best_out = best;
+        *best_us = best_ms * 1e3f / (float)reps;
+    }
     return e;
 }
 
@@ -525,9 +569,7 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                        n_schedules, BatchBounds{in_bytes, out_bytes}, ws, skipped_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_bitslice_kernel<TDES_BATCH_KMAX, TDES_BATCH_MIN_WAVES>), dim3(batch_grid_blocks()), dim3(kThreads), 0, stream,
-                       msgs, (uint32_t)n_msgs, schedules, (uint32_t)n_schedules, in, out, ws);
-    return hipGetLastError();
+    return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);
 }
 
 }  // namespace tdes

@@ -3,6 +3,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include <hip/hip_runtime_api.h>
 
 #include "keysched_core.h"
@@ -70,6 +72,34 @@ hipError_t launch_bitslice_cbc_dec(const BitsliceKeys &k, uint32_t iv0, uint32_t
                                    const uint8_t *in, uint8_t *out, size_t nbytes,
                                    hipStream_t stream);
 size_t batch_workspace_bytes(size_t n_msgs);
+
+// Configuration of the batched cipher: the compiled variant (kmax messages
+// per mask-table group, waves per SIMD) and the grid in multiples of the
+// workgroups that fit at once.
+struct BatchConfig {
+    int kmax, waves, grid_mult;
+};
+bool batch_config_valid(const BatchConfig &c);  // a compiled variant, grid_mult 1..4
+BatchConfig batch_config_default();
+// Every valid configuration (variants x multipliers), up to cap; returns
+// their number.
+int batch_config_list(BatchConfig *out, int cap);
+// The configuration batched launches use on the current device: set by
+// batch_config_set, else on first use the tuning cache's entry for this
+// device kind, else the default.
+hipError_t batch_config_current(BatchConfig *out);
+hipError_t batch_config_set(const BatchConfig &c);
+// Write c as this device kind's entry of the tuning cache (true if written,
+// or if the cache is switched off).
+bool batch_config_persist(const BatchConfig &c, double us_per_batch);
+// The tuning cache file: $TDES_TUNE_CACHE ("" = none), else
+// $XDG_CACHE_HOME/tdes/batch_tune.json, else ~/.cache/tdes/batch_tune.json.
+std::string tune_cache_path();
+// Entry of (device, cus) in the cache file at path: 1 found (and valid),
+// 0 none, -1 bad arguments.
+int cache_load(const char *path, const char *device, long cus, BatchConfig *out);
+bool cache_save(const char *path, const char *device, long cus, const BatchConfig &c,
+                double us_per_batch);
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream);
 // The batched cipher alone, for a workspace whose first-slice table the
 // caller filled already ([0] total slices, [1] 0, [2 + i] first slice of
@@ -84,14 +114,14 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                         size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
                         uint64_t out_bytes, uint64_t *ws, uint64_t *skipped_out,
                         hipStream_t stream);
-// Times the batch (scan + cipher, `reps` runs after one warm run) at grids
-// of 1..4 times the resident workgroups on `stream`, keeps the fastest for
-// later batched launches on the current device and returns its multiplier.
+// Times the batch (scan + cipher, `reps` runs after one warm run) in every
+// configuration on `stream`, keeps the fastest for later batched launches
+// on the current device and returns it with its time per batch (us).
 // Synchronous.
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                           size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
                           uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
-                          int *mult_out);
+                          BatchConfig *best, float *best_us);
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 

@@ -488,6 +488,24 @@ tdes_status tdes_server_release(tdes_server *s, void *d_out) {
     return TDES_OK;
 }
 
+tdes_status tdes_server_release_many(tdes_server *s, void *const *d_outs, size_t n,
+                                     size_t *n_released) {
+    if (s == nullptr || (d_outs == nullptr && n > 0)) return fail(TDES_ERR_ARG, "NULL argument");
+    size_t k = 0;
+    tdes_status st = TDES_OK;
+    for (size_t i = 0; i < n; i++) {
+        if (tdes_server_release(s, d_outs[i]) == TDES_OK) {
+            k++;
+        } else if (st == TDES_OK) {
+            char msg[96];
+            snprintf(msg, sizeof msg, "entry %zu is not a live result", i);
+            st = fail(TDES_ERR_ARG, msg);
+        }
+    }
+    if (n_released != nullptr) *n_released = k;
+    return st;
+}
+
 tdes_status tdes_server_get_stats(const tdes_server *s, tdes_server_stats *out) {
     if (s == nullptr || out == nullptr) return fail(TDES_ERR_ARG, "NULL argument");
     *out = s->st;

@@ -63,6 +63,9 @@ def _lib():
         L.tdes_server_progress.restype = ctypes.c_int
         L.tdes_server_release.argtypes = [vp, vp]
         L.tdes_server_release.restype = ctypes.c_int
+        L.tdes_server_release_many.argtypes = [vp, vp, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        L.tdes_server_release_many.restype = ctypes.c_int
         L.tdes_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.tdes_server_get_stats.restype = ctypes.c_int
         L.tdes_server_now.argtypes = []
@@ -115,6 +118,14 @@ class Server:
     def release(self, d_out):
         tdes._check(_lib().tdes_server_release(self.h, ctypes.c_void_p(int(d_out))))
 
+    def release_many(self, d_outs):
+        """Release many results at once (array-like of device addresses);
+        returns how many were released."""
+        a = np.ascontiguousarray(d_outs, dtype=np.uint64)
+        k = ctypes.c_size_t()
+        tdes._check(_lib().tdes_server_release_many(self.h, a.ctypes.data, len(a), ctypes.byref(k)))
+        return k.value
+
     def stats(self):
         st = ServerStats()
         tdes._check(_lib().tdes_server_get_stats(self.h, ctypes.byref(st)))
@@ -166,9 +177,9 @@ def run_open_loop(server, reqs, arrival, on_complete=None, timeout_s=60.0):
             status[tags] = comp["status"]
             if on_complete is not None:
                 on_complete(comp)
-            for c in comp:
-                if c["status"] == 0 and c["nbytes"] > 0:
-                    server.release(c["d_out"])
+            live = comp["d_out"][(comp["status"] == 0) & (comp["nbytes"] > 0)]
+            if len(live):
+                server.release_many(live)
             done += len(comp)
     wall = now() - t0
     return lat, status, wall, server.stats()

@@ -25,9 +25,11 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_probe_copy", "tdes_schedule_upload", "tdes_schedule_expand",
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
-           "tdes_server_release", "tdes_server_get_stats", "tdes_server_now", "tdes_ecb_host",
+           "tdes_server_release", "tdes_server_release_many", "tdes_server_get_stats",
+           "tdes_server_now", "tdes_ecb_host",
            "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_paper_design",
-           "tdes_batch_autotune")
+           "tdes_batch_autotune", "tdes_batch_get_config",
+           "tdes_batch_set_config", "tdes_batch_config_load", "tdes_batch_config_save")
 
 DEVICE_SCHEDULE_BYTES = 800
 MSG_BYTES = 32
@@ -48,6 +50,15 @@ class Schedule(ctypes.Structure):
 
 
 _lib = None
+
+
+class BatchConfig(ctypes.Structure):
+    """tdes_batch_config: the batched kernel's variant and grid."""
+    _fields_ = [("kmax", ctypes.c_uint32), ("waves", ctypes.c_uint32),
+                ("grid_mult", ctypes.c_uint32), ("saved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 def lib():
@@ -80,9 +91,20 @@ def lib():
         L.tdes_batch_workspace_bytes.restype = sz
         L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp]
         L.tdes_batch_submit.restype = ctypes.c_int
+        cfg_p = ctypes.POINTER(BatchConfig)
         L.tdes_batch_autotune.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp,
-                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+                                          ctypes.c_int, cfg_p]
         L.tdes_batch_autotune.restype = ctypes.c_int
+        L.tdes_batch_get_config.argtypes = [cfg_p]
+        L.tdes_batch_get_config.restype = ctypes.c_int
+        L.tdes_batch_set_config.argtypes = [cfg_p]
+        L.tdes_batch_set_config.restype = ctypes.c_int
+        L.tdes_batch_config_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_uint32,
+                                             cfg_p]
+        L.tdes_batch_config_load.restype = ctypes.c_int
+        L.tdes_batch_config_save.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_uint32,
+                                             cfg_p, ctypes.c_double]
+        L.tdes_batch_config_save.restype = ctypes.c_int
         L.tdes_ctr_crypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
         L.tdes_ctr_crypt.restype = ctypes.c_int
         L.tdes_cbc_decrypt.argtypes = [sched_p, ctypes.POINTER(ctypes.c_uint8), vp, vp, sz, vp]
@@ -343,6 +365,32 @@ def batch_submit_ptr(d_msgs, n_msgs, d_sched, n_sched, d_in, in_bytes, d_out, ou
                                    ws_bytes, ctypes.c_void_p(stream)))
 
 
+def batch_get_config():
+    """The batched kernel's configuration on the current device (a dict)."""
+    c = BatchConfig()
+    _check(lib().tdes_batch_get_config(ctypes.byref(c)))
+    return c.as_dict()
+
+
+def batch_set_config(kmax, waves, grid_mult):
+    _check(lib().tdes_batch_set_config(ctypes.byref(BatchConfig(kmax, waves, grid_mult, 0))))
+
+
+def batch_config_load(path, device, cus):
+    """The tuning cache's entry for (device, cus) as a dict, or None."""
+    c = BatchConfig()
+    r = lib().tdes_batch_config_load(path.encode(), device.encode(), cus, ctypes.byref(c))
+    if r < 0:
+        _check(r)
+    return c.as_dict() if r == 1 else None
+
+
+def batch_config_save(path, device, cus, kmax, waves, grid_mult, us_per_batch=0.0):
+    _check(lib().tdes_batch_config_save(path.encode(), device.encode(), cus,
+                                        ctypes.byref(BatchConfig(kmax, waves, grid_mult, 0)),
+                                        float(us_per_batch)))
+
+
 def msg_table(in_off, out_off, nbytes, sched_idx, dirs):
     """Descriptor array (numpy, n x 4 int64 = n tdes_msg) from per-message fields."""
     import numpy as np
@@ -386,18 +434,19 @@ class Batch:
         return out
 
     def autotune(self, x, out, reps=3, stream=None):
-        """Time this batch at grids of 1..4 times the resident workgroups and
-        keep the fastest for later batched launches on this device; returns
-        the chosen multiplier (synchronous).  x and out must not overlap."""
-        m = ctypes.c_int(0)
+        """Time this batch in every batched-kernel configuration and keep the
+        fastest for later batched launches on this device (and in the tuning
+        cache); returns it as a dict (synchronous).  x and out must not
+        overlap."""
+        c = BatchConfig()
         _check(lib().tdes_batch_autotune(
             ctypes.c_void_p(self.msgs.data_ptr()), self.n_msgs, ctypes.c_void_p(self.sched.data_ptr()),
             self.n_sched, ctypes.c_void_p(x.data_ptr()), x.numel(),
             ctypes.c_void_p(out.data_ptr()), out.numel(),
             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
             ctypes.c_void_p(_stream_handle(stream) if stream is not None else self.stream),
-            int(reps), ctypes.byref(m)))
-        return m.value
+            int(reps), ctypes.byref(c)))
+        return c.as_dict()
 
     def skipped(self):
         """Messages the last submit skipped as invalid (synchronises)."""

@@ -250,6 +250,69 @@ def test_batch_replays_in_a_captured_graph(torch_dev):
         assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
 
 
+@pytest.fixture(autouse=True)
+def _tune_cache(tmp_path, monkeypatch):
+    # the tuner's cache file goes to a scratch path, never the user's cache
+    monkeypatch.setenv("TDES_TUNE_CACHE", str(tmp_path / "tune.json"))
+
+
+def test_every_configuration_gives_the_same_bytes(torch_dev):
+    # Every compiled variant (messages per mask table x waves per SIMD) at
+    # every grid multiplier: the same output, equal to the oracle's.  The
+    # batch mixes many tiny messages (waves spanning more messages than one
+    # mask table holds) with longer ones.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x30D)
+    n = 700
+    lengths = np.where(g.random(n) < 0.7, g.integers(1, 9, size=n) * 8,
+                       g.integers(1, 600, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    data = W.uniform_bytes(g, int(lengths.sum()))
+    offs, want, b = _run_batch(torch, keys, lengths, dirs, data)
+    for i in range(0, n, 7):
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(want[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+    x = torch.from_numpy(data).cuda()
+    keep = T.batch_get_config()
+    try:
+        for kmax in (4, 8, 16):
+            for waves in (3, 4):
+                for mult in (1, 2, 3, 4):
+                    _say("batch config", kmax, waves, mult)
+                    T.batch_set_config(kmax, waves, mult)
+                    out = torch.full_like(x, 0xA5)
+                    b.submit(x, out)
+                    torch.cuda.synchronize()
+                    assert np.array_equal(out.cpu().numpy(), want), (kmax, waves, mult)
+    finally:
+        T.batch_set_config(keep["kmax"], keep["waves"], keep["grid_mult"])
+
+
+def test_autotune_writes_the_cache(torch_dev, tmp_path):
+    # The winner is written under this device's architecture name and CU
+    # count; loading that entry gives the configuration now in use.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x30E)
+    n = 200
+    lengths = (g.integers(1, 300, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    data = W.uniform_bytes(g, int(lengths.sum()))
+    offs, want, b = _run_batch(torch, keys, lengths, dirs, data)
+    x = torch.from_numpy(data).cuda()
+    out = torch.empty_like(x)
+    m = b.autotune(x, out, reps=1)
+    assert m["saved"] == 1
+    prop = torch.cuda.get_device_properties(0)
+    got = T.batch_config_load(str(tmp_path / "tune.json"), prop.gcnArchName,
+                              prop.multi_processor_count)
+    assert got is not None, open(str(tmp_path / "tune.json")).read()
+    assert (got["kmax"], got["waves"], got["grid_mult"]) == (m["kmax"], m["waves"], m["grid_mult"])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 def test_batch_autotune_keeps_results(torch_dev):
     # The autotuner runs the batch at several grids; every run, and every
     # later submit at the chosen grid, gives the same bytes.
@@ -266,7 +329,9 @@ def test_batch_autotune_keeps_results(torch_dev):
     out = torch.full_like(x, 0xA5)
     _say("batch autotune")
     m = b.autotune(x, out, reps=2)
-    assert m in (1, 2, 3, 4)
+    assert m["grid_mult"] in (1, 2, 3, 4) and m["kmax"] in (4, 8, 16) and m["waves"] in (3, 4)
+    cur = T.batch_get_config()
+    assert (cur["kmax"], cur["waves"], cur["grid_mult"]) == (m["kmax"], m["waves"], m["grid_mult"])
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), want)
     out2 = torch.full_like(x, 0x5A)

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol():
     assert sorted(T.SYMBOLS) == declared
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.tdes_abi_version() == 2
+    assert lib.tdes_abi_version() == 3
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -142,7 +142,7 @@ def test_cbc_argument_errors():
 
 def test_batch_autotune_argument_errors():
     lib = T.lib()
-    m = ctypes.c_int(0)
+    m = T.BatchConfig()
     a = ctypes.c_void_p(0x1000)
 
     def call(n=4, reps=2, out=ctypes.byref(m), ws=0x1000, ws_bytes=1 << 20, msgs=0x1000,
@@ -182,6 +182,58 @@ def test_batch_submit_argument_errors():
     assert call(sched=0x1008) == -3     # schedules must be 16-byte aligned
     assert call(d_in=0x100004) == -3
     assert call(msgs=0) == -1
+
+
+def test_batch_config_cache_file(tmp_path):
+    # The tuning cache: entries keyed by architecture name and CU count,
+    # written and read back, other entries kept, invalid ones ignored.
+    path = str(tmp_path / "sub" / "tune.json")
+    assert T.batch_config_load(path, "gfx950:sramecc+:xnack-", 256) is None  # no file
+    T.batch_config_save(path, "gfx950:sramecc+:xnack-", 256, 4, 4, 3, 201.5)
+    T.batch_config_save(path, "gfx950:sramecc+:xnack-", 128, 16, 3, 1, 99.0)
+    T.batch_config_save(path, "gfx942:sramecc+:xnack-", 304, 8, 4, 2)
+    got = T.batch_config_load(path, "gfx950:sramecc+:xnack-", 256)
+    assert (got["kmax"], got["waves"], got["grid_mult"]) == (4, 4, 3)
+    got = T.batch_config_load(path, "gfx950:sramecc+:xnack-", 128)
+    assert (got["kmax"], got["waves"], got["grid_mult"]) == (16, 3, 1)
+    assert T.batch_config_load(path, "gfx950:sramecc+:xnack-", 255) is None  # CU count differs
+    assert T.batch_config_load(path, "gfx950", 256) is None                  # name differs
+    # replacing an entry keeps the others
+    T.batch_config_save(path, "gfx950:sramecc+:xnack-", 256, 8, 3, 4, 180.0)
+    got = T.batch_config_load(path, "gfx950:sramecc+:xnack-", 256)
+    assert (got["kmax"], got["waves"], got["grid_mult"]) == (8, 3, 4)
+    assert T.batch_config_load(path, "gfx942:sramecc+:xnack-", 304)["kmax"] == 8
+    text = open(path).read()
+    assert text.count('"device"') == 3 and text.startswith('{"format": "tdes-batch-tune-1"')
+    import json
+    doc = json.loads(text)  # the file is valid JSON
+    assert len(doc["entries"]) == 3
+    # configurations that are not compiled variants are refused, and ignored
+    # when found in a file
+    with pytest.raises(T.TdesError):
+        T.batch_config_save(path, "gfx950", 256, 5, 4, 2)
+    with pytest.raises(T.TdesError):
+        T.batch_config_save(path, "gfx950", 256, 8, 4, 9)
+    with pytest.raises(T.TdesError):
+        T.batch_config_save(path, 'gfx"950', 256, 8, 4, 2)
+    with pytest.raises(T.TdesError):
+        T.batch_config_save("", "gfx950", 256, 8, 4, 2)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [\n{"device": "gfx950", "cus": 256, "kmax": 5, "waves": 4, '
+                   '"grid_mult": 2},\n{"device": "gfx950", "cus": 256, "kmax": 8}\n]}\n')
+    assert T.batch_config_load(str(bad), "gfx950", 256) is None
+    bad.write_text("not json at all\n")
+    assert T.batch_config_load(str(bad), "gfx950", 256) is None
+
+
+def test_batch_config_needs_a_device_or_a_valid_value():
+    lib = T.lib()
+    c = T.BatchConfig(5, 4, 2, 0)
+    assert lib.tdes_batch_set_config(ctypes.byref(c)) == -1   # not a compiled variant
+    c = T.BatchConfig(8, 4, 0, 0)
+    assert lib.tdes_batch_set_config(ctypes.byref(c)) == -1   # grid multiplier 0
+    assert lib.tdes_batch_set_config(None) == -1
+    assert lib.tdes_batch_get_config(None) == -1
 
 
 def _crypt_msg(n, a, b):

@@ -172,3 +172,25 @@ def test_failed_launch_completes_its_requests_with_an_error():
     st = s.stats()
     assert st["in_flight_bytes"] == 0 and st["arena_used_bytes"] == 0
     assert st["completed"] == 9 and st["failed"] == 3
+
+
+def test_release_many():
+    s = _server(slots=1, max_batch_msgs=8, test_polls=1)
+    s.submit(_reqs([512] * 6))
+    c = []
+    for _ in range(5):
+        c += list(s.progress())
+        if len(c) == 6:
+            break
+    outs = [int(x["d_out"]) for x in c]
+    assert s.release_many(outs[:3]) == 3
+    st = s.stats()
+    assert st["released"] == 3 and st["arena_used_bytes"] == 3 * 512
+    # a stale entry among live ones: the live ones are still released and the
+    # call reports the first bad entry
+    with pytest.raises(T.TdesError) as e:
+        s.release_many([outs[3], outs[0], outs[4], outs[5]])
+    assert "entry 1" in str(e.value)
+    st = s.stats()
+    assert st["released"] == 6 and st["arena_used_bytes"] == 0 and st["in_flight_bytes"] == 0
+    assert s.release_many([]) == 0

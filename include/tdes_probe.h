@@ -8,8 +8,9 @@
  * wave64 VALU instruction over four cycles and may issue a second one from
  * another wave in the same four cycles, for some opcodes only; these probes
  * measure the sustained lane-operation rate per opcode (rocprofv3 counters
- * SQ_INSTS_VALU / SQ_ACTIVE_INST_VALU2 give the pairing directly), and the
- * HBM bandwidth of a plain copy (also the reference kernel whose memory
+ * SQ_INSTS_VALU / SQ_ACTIVE_INST_VALU2 give the pairing directly), the LDS
+ * read rate (the table kernel's other ceiling; SQ_LDS_BANK_CONFLICT shows
+ * the conflicts of each pattern), and the HBM bandwidth of a plain copy (also the reference kernel whose memory
  * counters calibrate the cipher's measured HBM traffic).
  *
  * Same conventions as tdes.h: device pointers owned by the caller, work
@@ -43,6 +44,21 @@ enum {
  * d_sink[block * 256 + thread] (d_sink holds blocks * 256 uint32).
  * Lane operations performed: blocks * 256 * 16 * iters. */
 int tdes_probe_valu(int op, uint32_t *d_sink, unsigned blocks, unsigned iters, void *stream);
+
+/* LDS read patterns for tdes_probe_lds. */
+enum {
+    TDES_PROBE_LDS_CONSEC = 0,   /* ds_read_b32, a wave's lanes on 64 consecutive words */
+    TDES_PROBE_LDS_SAMEBANK = 1, /* ds_read_b32, all lanes of a read in one bank        */
+    TDES_PROBE_LDS_BCAST = 2,    /* ds_read_b32, all lanes on one word (broadcast)      */
+    TDES_PROBE_LDS_B128 = 3      /* ds_read_b128, 64 consecutive 16-byte pieces          */
+};
+
+/* Launch `blocks` workgroups of 256 threads, each with a 64 KiB LDS table;
+ * every thread issues 16 * iters LDS reads of pattern `mode`, then writes
+ * one word to d_sink[block * 256 + thread] (d_sink holds blocks * 256
+ * uint32).  Bytes read from LDS: blocks * 256 * 16 * iters * 4 (16 for
+ * TDES_PROBE_LDS_B128). */
+int tdes_probe_lds(int mode, uint32_t *d_sink, unsigned blocks, unsigned iters, void *stream);
 
 /* Copy nbytes (multiple of 16; both pointers 16-byte aligned; buffers
  * must not overlap) from d_in to d_out with 16-byte vector loads/stores. */

@@ -22,7 +22,7 @@ STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR
 # Exported symbols, checked against include/*.h by the tests.
 SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
            "tdes_last_error", "tdes_abi_version", "tdes_kernel_key_bytes", "tdes_probe_valu",
-           "tdes_probe_copy", "tdes_schedule_upload", "tdes_schedule_expand",
+           "tdes_probe_copy", "tdes_probe_lds", "tdes_schedule_upload", "tdes_schedule_expand",
            "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
            "tdes_server_release", "tdes_server_release_many", "tdes_server_get_stats",
@@ -117,6 +117,8 @@ def lib():
         L.tdes_kernel_key_bytes.restype = ctypes.c_long
         L.tdes_probe_valu.argtypes = [ctypes.c_int, vp, ctypes.c_uint, ctypes.c_uint, vp]
         L.tdes_probe_valu.restype = ctypes.c_int
+        L.tdes_probe_lds.argtypes = [ctypes.c_int, vp, ctypes.c_uint, ctypes.c_uint, vp]
+        L.tdes_probe_lds.restype = ctypes.c_int
         L.tdes_probe_copy.argtypes = [vp, vp, sz, vp]
         L.tdes_probe_copy.restype = ctypes.c_int
         _lib = L

@@ -13,7 +13,8 @@ bitsliced (per 32 blocks = one lane):
   IP, E, P and FP are register renaming: no operations.
 table (SP-box) kernel (per block):
   48 rounds x (1 rotate + 4 key XORs + 8 index extracts + 8 XORs)
-  + IP and FP rotate-and-mask groups (2 ops each); plus 8 LDS reads a round.
+  + IP and FP as delta swaps (the operation counts the generator writes
+  beside them); plus 8 LDS reads a round.
 HBM traffic: every block is read once and written once: 16 bytes.
 """
 import os
@@ -55,8 +56,8 @@ def bitslice_ops_per_block():
 
 def spbox_ops_per_block():
     text = _read("spbox_gen.h")
-    groups = sum(int(g) for g in re.findall(r"\((\d+) rotate-and-mask groups\)", text))
-    return 48 * (1 + 4 + 8 + 8) + 2 * groups
+    ipfp = sum(int(g) for g in re.findall(r"\((\d+) operations\)", text))
+    return 48 * (1 + 4 + 8 + 8) + ipfp
 
 
 def ops_per_block(kernel):

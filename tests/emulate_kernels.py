@@ -149,17 +149,35 @@ def _rotl(x, s):
 
 
 def _run_macro(text, name, env):
-    """Execute one of the generated IP/FP macros on Python ints."""
+    """Execute one of the generated IP/FP macros on Python ints (32-bit
+    unsigned arithmetic: every variable is reduced mod 2^32 after each
+    statement, as C's uint32_t would be)."""
     m = re.search(r"#define %s\([^)]*\) do \{ \\\n(.*?)\} while \(0\)" % name, text, re.S)
+    glb = {"rotr": lambda x, s: ((x >> s) | (x << (32 - s))) & M32,
+           "bswap": lambda x: int.from_bytes(int(x).to_bytes(4, "little"), "big")}
     for line in m.group(1).split("\\\n"):
-        line = line.strip().rstrip(";")
-        if not line:
-            continue
-        line = re.sub(r"__builtin_amdgcn_alignbit\((\w+), \w+, (\d+)\)",
-                      lambda mm: "rotr(%s, %s)" % (mm.group(1), mm.group(2)), line)
-        line = line.replace("0u", "0").replace("u ", " ")
-        line = re.sub(r"(0x[0-9a-f]+)u", r"\1", line)
-        exec(line, {"rotr": lambda x, s: ((x >> s) | (x << (32 - s))) & M32}, env)
+        for stmt in line.split(";"):
+            stmt = stmt.strip()
+            if not stmt:
+                continue
+            stmt = re.sub(r"__builtin_amdgcn_alignbit\((\w+), \w+, (\d+)\)",
+                          lambda mm: "rotr(%s, %s)" % (mm.group(1), mm.group(2)), stmt)
+            stmt = stmt.replace("__builtin_bswap32", "bswap")
+            stmt = re.sub(r"(0x[0-9a-f]+)u", r"\1", stmt)
+            stmt = re.sub(r"\b(\d+)u\b", r"\1", stmt)
+            if stmt.startswith("uint32_t "):
+                # a declaration: "uint32_t a = X, b = Y, t"
+                decls = []
+                for part in stmt[len("uint32_t "):].split(", "):
+                    if "=" in part:
+                        decls.append(part)
+                for d in decls:
+                    exec(d, glb, env)
+            else:
+                exec(stmt, glb, env)
+            for k, v in list(env.items()):
+                if isinstance(v, int):
+                    env[k] = v & M32
     return env
 
 

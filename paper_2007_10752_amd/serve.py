@@ -185,11 +185,23 @@ def run_open_loop(server, reqs, arrival, on_complete=None, timeout_s=60.0):
     return lat, status, wall, server.stats()
 
 
+# request size bands for the latency breakdown: up to 1 KiB, up to 64 KiB, larger
+BANDS = (("small", 0, 1024), ("medium", 1025, 65536), ("large", 65537, 1 << 62))
+
+
 def summarize(lat, sizes, wall, stats, rate, duration):
     ok = lat[~np.isnan(lat)]
+    by_band = {}
+    for name, lo, hi in BANDS:
+        sel = (sizes >= lo) & (sizes <= hi) & ~np.isnan(lat)
+        if sel.any():
+            by_band[name] = {"n": int(sel.sum()),
+                             "p50_ms": round(float(np.percentile(lat[sel], 50)) * 1e3, 4),
+                             "p99_ms": round(float(np.percentile(lat[sel], 99)) * 1e3, 4)}
     return {"rate_req_s": rate, "duration_s": duration, "requests": int(len(lat)),
             "p50_ms": round(float(np.percentile(ok, 50)) * 1e3, 4),
             "p99_ms": round(float(np.percentile(ok, 99)) * 1e3, 4),
+            "by_size": by_band,
             "GBps": round(float(np.sum(sizes)) / wall / 1e9, 4),
             "offered_GBps": round(float(np.sum(sizes)) / duration / 1e9, 4),
             "batches": stats["batches"],

@@ -189,6 +189,29 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
                               void *d_out_base, size_t out_bytes, void *d_workspace,
                               size_t workspace_bytes, void *stream);
 
+/* Most messages one tdes_batch_submit_noalloc call takes. */
+#define TDES_BATCH_NOALLOC_MAX_MSGS (1u << 20)
+
+/* tdes_batch_submit without a caller workspace and without any allocation,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * descriptor scan's table lives in a fixed array in the library's device
+ * memory (8 MiB + 24 bytes: room for TDES_BATCH_NOALLOC_MAX_MSGS messages),
+ * one per device, held until the process ends; its address is looked up on
+ * the first call on each device.  Nothing in it must start at zero: the
+ * scan rewrites what the cipher reads on every call.  Every call on a device
+ * shares that device's array, so calls whose work overlaps in time on one
+ * device (other streams, other threads) race and their results are
+ * unspecified: serialise them, for example on one stream.  Arguments, checks
+ * and results as for tdes_batch_submit, except: d_skipped (device memory,
+ * 8-byte aligned, or NULL) receives the number of skipped messages, and
+ * n_msgs > TDES_BATCH_NOALLOC_MAX_MSGS is TDES_ERR_ARG.  Calls no hipMalloc
+ * or hipFree. */
+tdes_status tdes_batch_submit_noalloc(const tdes_msg *d_msgs, size_t n_msgs,
+                                      const void *d_schedules, size_t n_schedules,
+                                      const void *d_in_base, size_t in_bytes, void *d_out_base,
+                                      size_t out_bytes, uint64_t *d_skipped, void *stream);
+
 /* ---- Host-resident form: data in host memory ----------------------------- */
 
 /* Most slots (device staging buffers, one stream each) tdes_ecb_host uses. */

@@ -274,6 +274,33 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
     return TDES_OK;
 }
 
+tdes_status tdes_batch_submit_noalloc(const tdes_msg *d_msgs, size_t n_msgs,
+                                      const void *d_schedules, size_t n_schedules,
+                                      const void *d_in_base, size_t in_bytes, void *d_out_base,
+                                      size_t out_bytes, uint64_t *d_skipped, void *stream) {
+    g_last_error.clear();
+    if (n_msgs == 0) return TDES_OK;
+    if (n_msgs > TDES_BATCH_NOALLOC_MAX_MSGS)
+        return fail(TDES_ERR_ARG, "%zu messages: at most %u per call without a workspace", n_msgs,
+                    (unsigned)TDES_BATCH_NOALLOC_MAX_MSGS);
+    tdes_status st = batch_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base, d_out_base);
+    if (st != TDES_OK) return st;
+    if ((uintptr_t)d_skipped % 8 != 0) return fail(TDES_ERR_ALIGN, "misaligned pointer");
+    uint64_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipError_t e = tdes::noalloc_workspace(&ws, &ws_bytes);
+    if (e != hipSuccess)
+        return fail(TDES_ERR_DEVICE, "no-alloc workspace: %s", hipGetErrorString(e));
+    if (ws_bytes < tdes::batch_workspace_bytes(n_msgs))  // guarded by the limit above
+        return fail(TDES_ERR_ARG, "no-alloc workspace too small");
+    e = tdes::launch_batch(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules), n_schedules,
+                           static_cast<const uint8_t *>(d_in_base), in_bytes,
+                           static_cast<uint8_t *>(d_out_base), out_bytes, ws, d_skipped,
+                           static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
+    return TDES_OK;
+}
+
 tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const void *d_schedules,
                                 size_t n_schedules, const void *d_in_base, size_t in_bytes,
                                 void *d_out_base, size_t out_bytes, void *d_workspace,

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "bitslice_core.h"
 #include "internal.h"
@@ -560,6 +561,39 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
 }
 
 size_t batch_workspace_bytes(size_t n_msgs) { return (kWsHeader + n_msgs + 1) * sizeof(uint64_t); }
+
+// The workspace of the no-allocation entry point: a fixed array in device
+// memory (each device holds its own copy), sized for TDES_BATCH_NOALLOC_MAX_MSGS
+// messages.  In host code its name is not a device address; the address is
+// looked up once per device (with that device current) and kept.
+static_assert(TDES_BATCH_NOALLOC_MAX_MSGS <= TDES_BATCH_MAX_MSGS, "no-alloc limit");
+constexpr size_t kNoAllocWords = kWsHeader + (size_t)TDES_BATCH_NOALLOC_MAX_MSGS + 1;
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+hipError_t noalloc_workspace(uint64_t **ws, size_t *ws_bytes) {
+    static std::atomic<uint64_t *> addr[kMaxDevices];
+    static std::mutex mu;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    uint64_t *p = addr[dev].load();
+    if (p == nullptr) {
+        std::lock_guard<std::mutex> g(mu);
+        p = addr[dev].load();
+        if (p == nullptr) {
+            void *sym = nullptr;
+            e = hipGetSymbolAddress(&sym, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (sym == nullptr) return hipErrorInvalidSymbol;
+            p = static_cast<uint64_t *>(sym);
+            addr[dev].store(p);
+        }
+    }
+    *ws = p;
+    *ws_bytes = kNoAllocWords * sizeof(uint64_t);
+    return hipSuccess;
+}
 
 hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                         size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,

@@ -114,6 +114,10 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                         size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
                         uint64_t out_bytes, uint64_t *ws, uint64_t *skipped_out,
                         hipStream_t stream);
+// The fixed device workspace of the no-allocation batched call on the
+// current device (its address, looked up on the first call on that device,
+// and its size in bytes).
+hipError_t noalloc_workspace(uint64_t **ws, size_t *ws_bytes);
 // Times the batch (scan + cipher, `reps` runs after one warm run) in every
 // configuration on `stream`, keeps the fastest for later batched launches
 // on the current device and returns it with its time per batch (us).

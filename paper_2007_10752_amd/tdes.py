@@ -23,7 +23,8 @@ STATUS = {0: "TDES_OK", -1: "TDES_ERR_ARG", -2: "TDES_ERR_LENGTH", -3: "TDES_ERR
 SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_crypt",
            "tdes_last_error", "tdes_abi_version", "tdes_kernel_key_bytes", "tdes_probe_valu",
            "tdes_probe_copy", "tdes_probe_lds", "tdes_schedule_upload", "tdes_schedule_expand",
-           "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_server_create",
+           "tdes_batch_workspace_bytes", "tdes_batch_submit", "tdes_batch_submit_noalloc",
+           "tdes_server_create",
            "tdes_server_destroy", "tdes_server_submit", "tdes_server_progress",
            "tdes_server_release", "tdes_server_release_many", "tdes_server_get_stats",
            "tdes_server_now", "tdes_ecb_host",
@@ -68,6 +69,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("%s is missing: build it with `python -m paper_2007_10752_amd.build`"
                                % LIB_PATH)
+        # torch ships its own HIP runtime under the same soname as the
+        # system's.  Whichever is loaded first serves the whole process;
+        # loading torch first makes it the one torch was built against, so
+        # the library and torch's tensors share one runtime (the other order
+        # left the library without a device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         sched_p = ctypes.POINTER(Schedule)
@@ -91,6 +101,8 @@ def lib():
         L.tdes_batch_workspace_bytes.restype = sz
         L.tdes_batch_submit.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp]
         L.tdes_batch_submit.restype = ctypes.c_int
+        L.tdes_batch_submit_noalloc.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, vp]
+        L.tdes_batch_submit_noalloc.restype = ctypes.c_int
         cfg_p = ctypes.POINTER(BatchConfig)
         L.tdes_batch_autotune.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp,
                                           ctypes.c_int, cfg_p]
@@ -365,6 +377,22 @@ def batch_submit_ptr(d_msgs, n_msgs, d_sched, n_sched, d_in, in_bytes, d_out, ou
                                    n_sched, ctypes.c_void_p(d_in), in_bytes,
                                    ctypes.c_void_p(d_out), out_bytes, ctypes.c_void_p(d_ws),
                                    ws_bytes, ctypes.c_void_p(stream)))
+
+
+# Most messages tdes_batch_submit_noalloc takes.
+BATCH_NOALLOC_MAX_MSGS = 1 << 20
+
+
+def batch_submit_noalloc_ptr(d_msgs, n_msgs, d_sched, n_sched, d_in, in_bytes, d_out, out_bytes,
+                             d_skipped=0, stream=0):
+    """tdes_batch_submit_noalloc on raw device addresses (no workspace;
+    d_skipped: device address of a uint64 for the skipped count, or 0)."""
+    _check(lib().tdes_batch_submit_noalloc(ctypes.c_void_p(d_msgs), n_msgs,
+                                           ctypes.c_void_p(d_sched), n_sched,
+                                           ctypes.c_void_p(d_in), in_bytes,
+                                           ctypes.c_void_p(d_out), out_bytes,
+                                           ctypes.c_void_p(d_skipped or None),
+                                           ctypes.c_void_p(stream)))
 
 
 def batch_get_config():

@@ -404,19 +404,57 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
     }
 }
 
-// One thread per (bundle, direction): the three key schedules, then the
-// 100 mask words of that direction.
-__global__ __launch_bounds__(256) void expand_kernel(const uint8_t *keys24, size_t n,
-                                                    uint32_t *schedules) {
-    const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= 2 * n) return;
-    const size_t b = g / 2;
-    const int dir = (int)(g % 2);
-    uint8_t key[24];
-    for (int i = 0; i < 24; i++) key[i] = keys24[24 * b + i];
-    uint64_t k[3][16];
-    for (int j = 0; j < 3; j++) des_round_keys(key + 8 * j, k[j]);
-    bitslice_mask_words(k, dir, schedules + b * kDeviceScheduleWords + dir * kDirWords);
+// Key expansion, one wave per bundle (four per workgroup), both directions.
+// The rounds are independent once each round key is computed on its own
+// (des_round_key), so lanes 0..47 each make one of the 48 round keys, then
+// the primary mask of one round per direction; the mask walk that links the
+// rounds is short and runs on every lane alike; lane t then forms the two
+// words of round t and lanes 48..51 the four extra words.  A wave finishes
+// in a few microseconds, so small batches (a request server's) do not wait
+// on one thread working through a whole bundle.
+constexpr int kExpandWaves = 4;
+
+__global__ __launch_bounds__(kExpandWaves * kWave) void expand_kernel(const uint8_t *keys24,
+                                                                      size_t n,
+                                                                      uint32_t *schedules) {
+    __shared__ uint64_t rk_s[kExpandWaves][48];
+    __shared__ uint32_t p_s[kExpandWaves][2][48];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const size_t b = (size_t)blockIdx.x * kExpandWaves + w;
+    const bool live = b < n;  // uniform per wave; every wave reaches the barriers
+    if (live && lane < 48) {
+        const uint8_t *kp = keys24 + 24 * b + 8 * (lane / 16);
+        uint8_t key[8];
+        for (int i = 0; i < 8; i++) key[i] = kp[i];
+        rk_s[w][lane] = des_round_key(key, lane % 16);
+    }
+    __syncthreads();
+    if (live && lane < 48)
+        for (int dir = 0; dir < 2; dir++)
+            p_s[w][dir][lane] = bs_primary_mask(rk_s[w][round_key_slot(dir, lane)]);
+    __syncthreads();
+    if (!live) return;
+    for (int dir = 0; dir < 2; dir++) {
+        uint32_t ms = 0, md = 0, nm = 0, extra[4];
+        bs_mask_walk(
+            p_s[w][dir],
+            [&](int t, uint32_t s0, uint32_t d0, uint32_t n0) {
+                if (t == lane) {
+                    ms = s0;
+                    md = d0;
+                    nm = n0;
+                }
+            },
+            extra);
+        uint32_t *out = schedules + b * kDeviceScheduleWords + dir * kDirWords;
+        if (lane < 48) {
+            out[2 * lane + 1] = bs_dup_word(ms, rk_s[w][round_key_slot(dir, lane)]);
+            out[2 * lane] = bs_comp_word(md, nm);
+        } else if (lane < 52) {
+            const int i = lane - 48;
+            out[96 + i] = i == 0 ? extra[0] : i == 1 ? extra[1] : i == 2 ? extra[2] : extra[3];
+        }
+    }
 }
 
 // The batched kernel's grid: grid_mult times the workgroups that fit at
@@ -456,26 +494,31 @@ int resident_blocks() {
     return v;
 }
 
+// (max_blocks: when the host knows the batch's slices, no more workgroups
+// than they fill; 0 = unknown)
 template <int K, int W>
-hipError_t launch_cipher_variant(int grid_mult, const tdes_msg *msgs, uint32_t n_msgs,
-                                 const uint32_t *sched, uint32_t n_sched, const uint8_t *in,
-                                 uint8_t *out, const uint64_t *ws, hipStream_t stream) {
-    hipLaunchKernelGGL((batch_bitslice_kernel<K, W>), dim3(resident_blocks<K, W>() * grid_mult),
-                       dim3(kThreads), 0, stream, msgs, n_msgs, sched, n_sched, in, out, ws);
+hipError_t launch_cipher_variant(int grid_mult, uint64_t max_blocks, const tdes_msg *msgs,
+                                 uint32_t n_msgs, const uint32_t *sched, uint32_t n_sched,
+                                 const uint8_t *in, uint8_t *out, const uint64_t *ws,
+                                 hipStream_t stream) {
+    uint64_t blocks = (uint64_t)resident_blocks<K, W>() * (uint64_t)grid_mult;
+    if (max_blocks != 0 && max_blocks < blocks) blocks = max_blocks;
+    hipLaunchKernelGGL((batch_bitslice_kernel<K, W>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       stream, msgs, n_msgs, sched, n_sched, in, out, ws);
     return hipGetLastError();
 }
 
 // The batched cipher in the current device's configuration.
 hipError_t launch_cipher(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sched,
                          size_t n_sched, const uint8_t *in, uint8_t *out, const uint64_t *ws,
-                         hipStream_t stream) {
+                         uint64_t max_blocks, hipStream_t stream) {
     BatchConfig c;
     const hipError_t e = batch_config_current(&c);
     if (e != hipSuccess) return e;
 #define TDES_LAUNCH_IF(K, W)                                                                   \
     if (c.kmax == K && c.waves == W)                                                           \
-        return launch_cipher_variant<K, W>(c.grid_mult, msgs, (uint32_t)n_msgs, sched,          \
-                                           (uint32_t)n_sched, in, out, ws, stream);
+        return launch_cipher_variant<K, W>(c.grid_mult, max_blocks, msgs, (uint32_t)n_msgs,     \
+                                           sched, (uint32_t)n_sched, in, out, ws, stream);
     TDES_BATCH_VARIANTS(TDES_LAUNCH_IF)
 #undef TDES_LAUNCH_IF
     return hipErrorInvalidValue;
@@ -505,17 +548,20 @@ int batch_config_list(BatchConfig *out, int cap) {
 }
 
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream) {
-    const size_t threads = 2 * n, blocks = (threads + 255) / 256;
+    const size_t blocks = (n + kExpandWaves - 1) / kExpandWaves;
     if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, keys24, n,
-                       schedules);
+    hipLaunchKernelGGL(expand_kernel, dim3((unsigned)blocks), dim3(kExpandWaves * kWave), 0, stream,
+                       keys24, n, schedules);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                                  size_t n_schedules, const uint8_t *in, uint8_t *out,
-                                 const uint64_t *ws, hipStream_t stream) {
-    return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);
+                                 const uint64_t *ws, uint64_t total_slices, hipStream_t stream) {
+    // a workgroup's waves take kWave consecutive slices each per step
+    const uint64_t per_block = (uint64_t)kWave * kWavesPerBlock;
+    const uint64_t need = total_slices == 0 ? 1 : (total_slices + per_block - 1) / per_block;
+    return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, need, stream);
 }
 
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
@@ -603,7 +649,7 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                        n_schedules, BatchBounds{in_bytes, out_bytes}, ws, skipped_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, stream);
+    return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, 0, stream);
 }
 
 }  // namespace tdes

@@ -103,10 +103,11 @@ bool cache_save(const char *path, const char *device, long cus, const BatchConfi
 hipError_t launch_expand(const uint8_t *keys24, size_t n, uint32_t *schedules, hipStream_t stream);
 // The batched cipher alone, for a workspace whose first-slice table the
 // caller filled already ([0] total slices, [1] 0, [2 + i] first slice of
-// message i, [2 + n] total; a message has ceil(nbytes / 256) slices).
+// message i, [2 + n] total; a message has ceil(nbytes / 256) slices).  The
+// grid is no larger than total_slices needs.
 hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
                                  size_t n_schedules, const uint8_t *in, uint8_t *out,
-                                 const uint64_t *ws, hipStream_t stream);
+                                 const uint64_t *ws, uint64_t total_slices, hipStream_t stream);
 // Descriptor scan (validation against the buffer sizes, first-slice table in
 // ws, skipped count in ws[1] and, if skipped_out is not NULL, there too),
 // then the batched cipher.

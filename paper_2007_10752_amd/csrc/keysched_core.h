@@ -57,59 +57,112 @@ TDES_HD inline void des_round_keys(const uint8_t key[8], uint64_t rk[16]) {
     }
 }
 
+// Round key i (0..15) of one 64-bit key on its own, without the rounds
+// before it: the halves are rotated once by the sum of the shift table
+// through round i (modulo 28, a full turn).  Equals rk[i] of des_round_keys.
+TDES_HD inline uint64_t des_round_key(const uint8_t key[8], int i) {
+    uint64_t k = 0;
+    for (int b = 0; b < 8; b++) k = (k << 8) | key[b];
+    const uint64_t cd = ks_gather(k, 64, kPC1, 56);
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; j++) s += j <= i ? (int)kShifts[j] : 0;
+    s %= 28;
+    const uint32_t c = ks_rotl28((uint32_t)(cd >> 28), s);
+    const uint32_t d = ks_rotl28((uint32_t)(cd & 0x0FFFFFFFu), s);
+    return ks_gather(((uint64_t)c << 28) | d, 56, kPC2, 48);
+}
+
 // Round t of the 48 a 3DES pass applies: encryption runs E_K1, D_K2, E_K3,
 // decryption D_K3, E_K2, D_K1 (Sec. III-B); a DES decryption uses the round
-// keys in reverse.  k[b][i] is round key i+1 of base key b+1.
-TDES_HD inline uint64_t round_key_at(const uint64_t (&k)[3][16], int dir, int t) {
+// keys in reverse.  Returns 16 * b + i for round key i+1 of base key b+1.
+TDES_HD inline int round_key_slot(int dir, int t) {
     const int st = t / 16, r = t % 16;
     const int key = dir ? 2 - st : st;
     const bool rev = dir ? (st != 1) : (st == 1);
-    return k[key][rev ? 15 - r : r];
+    return 16 * key + (rev ? 15 - r : r);
+}
+
+// k[b][i] is round key i+1 of base key b+1.
+TDES_HD inline uint64_t round_key_at(const uint64_t (&k)[3][16], int dir, int t) {
+    const int slot = round_key_slot(dir, t);
+    return k[slot / 16][slot % 16];
 }
 
 TDES_HD inline bool bs_dest_is_x(int t) { return ((t / 16) % 2 == 0) == (t % 2 == 0); }
 
-// The 100 mask words of direction dir for round keys k.
-TDES_HD inline void bitslice_mask_words(const uint64_t (&k)[3][16], int dir, uint32_t *w) {
-    for (int i = 0; i < kDirWords; i++) w[i] = 0;
-    uint32_t mx = 0, my = 0;  // current mask bit of each word of X and Y
-    uint64_t cur = round_key_at(k, dir, 0);
-    for (int i = 0; i < 32; i++) my |= (uint32_t)((cur >> (47 - kBsPrimaryE[i])) & 1u) << i;
-    w[96] = my;
+// Round u > t that next reads the half round t updates (-1: none).
+TDES_HD inline int bs_next_reader(int t) {
+    for (int u = t + 1; u < 48; u++)
+        if (bs_dest_is_x(u) != bs_dest_is_x(t)) return u;
+    return -1;
+}
+
+// Bit i: the key bit at the primary expansion position of half-word i.
+TDES_HD inline uint32_t bs_primary_mask(uint64_t rk) {
+    uint32_t m = 0;
+    for (int i = 0; i < 32; i++) m |= (uint32_t)((rk >> (47 - kBsPrimaryE[i])) & 1u) << i;
+    return m;
+}
+
+// Word 2t + 1: bit q is the key difference for the q-th second-use input,
+// given the source half's mask ms and round key cur of round t.
+TDES_HD inline uint32_t bs_dup_word(uint32_t ms, uint64_t cur) {
+    uint32_t dup = 0;
+    for (int q = 0; q < 16; q++) {
+        const int e = kBsDupE[q];
+        dup |= (((ms >> kBsESrc[e]) & 1u) ^ (uint32_t)((cur >> (47 - e)) & 1u)) << q;
+    }
+    return dup;
+}
+
+// Word 2t: bit o swaps the mask of the half-word S-box output o lands in,
+// from md (before round t) to nm (its next use).
+TDES_HD inline uint32_t bs_comp_word(uint32_t md, uint32_t nm) {
+    uint32_t comp = 0;
+    for (int o = 0; o < 32; o++) comp |= (((md ^ nm) >> kBsOutWord[o]) & 1u) << o;
+    return comp;
+}
+
+// The masks the halves carry through the 48 rounds, from the primary masks
+// P[t] of the rounds' keys: f(t, ms, md, nm) for every round (ms: mask of
+// the source half when round t reads it; md, nm: mask of the destination
+// half before and after round t), and the four extra words (initial mask of
+// Y, re-masks before rounds 16 and 32, final mask of X).  Only this walk is
+// sequential; the words of different rounds can be formed in parallel.
+template <class F>
+TDES_HD inline void bs_mask_walk(const uint32_t *P, F &&f, uint32_t extra[4]) {
+    uint32_t mx = 0, my = P[0];  // current mask of each half
+    extra[0] = my;
     for (int t = 0; t < 48; t++) {
         const bool dx = bs_dest_is_x(t);
         uint32_t &ms = dx ? my : mx;
         uint32_t &md = dx ? mx : my;
-        cur = round_key_at(k, dir, t);
         if (t == 16 || t == 32) {
-            uint32_t m = 0;
-            for (int i = 0; i < 32; i++) m |= (uint32_t)((cur >> (47 - kBsPrimaryE[i])) & 1u) << i;
-            w[t == 16 ? 97 : 98] = ms ^ m;
-            ms = m;
+            extra[t == 16 ? 1 : 2] = ms ^ P[t];
+            ms = P[t];
         }
-        uint32_t dup = 0;
-        for (int q = 0; q < 16; q++) {
-            const int e = kBsDupE[q];
-            dup |= (((ms >> kBsESrc[e]) & 1u) ^ (uint32_t)((cur >> (47 - e)) & 1u)) << q;
-        }
-        w[2 * t + 1] = dup;
-        int next = -1;  // next round reading the half updated now
-        for (int u = t + 1; u < 48 && next < 0; u++)
-            if (bs_dest_is_x(u) != dx) next = u;
-        uint32_t nm = 0;
-        if (next >= 0) {
-            const uint64_t nk = round_key_at(k, dir, next);
-            for (int i = 0; i < 32; i++) nm |= (uint32_t)((nk >> (47 - kBsPrimaryE[i])) & 1u) << i;
-        }
-        uint32_t comp = 0;
-        for (int o = 0; o < 32; o++) {
-            const int i = kBsOutWord[o];
-            comp |= (((md ^ nm) >> i) & 1u) << o;
-        }
-        w[2 * t] = comp;
+        const int next = bs_next_reader(t);
+        const uint32_t nm = next >= 0 ? P[next] : 0u;
+        f(t, ms, md, nm);
         md = nm;
     }
-    w[99] = mx;
+    extra[3] = mx;
+}
+
+// The 100 mask words of direction dir for round keys k.
+TDES_HD inline void bitslice_mask_words(const uint64_t (&k)[3][16], int dir, uint32_t *w) {
+    uint32_t P[48];
+    for (int t = 0; t < 48; t++) P[t] = bs_primary_mask(round_key_at(k, dir, t));
+    uint32_t extra[4];
+    bs_mask_walk(
+        P,
+        [&](int t, uint32_t ms, uint32_t md, uint32_t nm) {
+            w[2 * t + 1] = bs_dup_word(ms, round_key_at(k, dir, t));
+            w[2 * t] = bs_comp_word(md, nm);
+        },
+        extra);
+    for (int i = 0; i < 4; i++) w[96 + i] = extra[i];
 }
 
 }  // namespace tdes

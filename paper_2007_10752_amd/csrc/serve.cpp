@@ -231,9 +231,13 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
         return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
     }
-    uint64_t *ws = reinterpret_cast<uint64_t *>(sl.h_stage + sl.lay.ws_off);
-    tdes_msg *msgs = reinterpret_cast<tdes_msg *>(sl.h_stage + sl.lay.msgs_off);
-    uint8_t *keys = sl.h_stage + sl.lay.keys_off;
+    // laid out for this batch's size (the buffers hold the largest batch), so
+    // the copy carries only what the batch uses
+    Staging lay;
+    lay.layout(n);
+    uint64_t *ws = reinterpret_cast<uint64_t *>(sl.h_stage + lay.ws_off);
+    tdes_msg *msgs = reinterpret_cast<tdes_msg *>(sl.h_stage + lay.msgs_off);
+    uint8_t *keys = sl.h_stage + lay.keys_off;
     uint64_t total = 0;
     for (size_t i = 0; i < n; i++) {
         const Active &a = sl.reqs[i];
@@ -251,15 +255,14 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
     ws[0] = total;
     ws[1] = 0;
     ws[2 + n] = total;
-    const size_t bytes = sl.lay.keys_off + 24 * n;
-    e = hipMemcpyAsync(sl.d_stage, sl.h_stage, bytes, hipMemcpyHostToDevice, sl.stream);
+    e = hipMemcpyAsync(sl.d_stage, sl.h_stage, lay.bytes, hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess)
-        e = tdes::launch_expand(sl.d_stage + sl.lay.keys_off, n, sl.d_sched, sl.stream);
+        e = tdes::launch_expand(sl.d_stage + lay.keys_off, n, sl.d_sched, sl.stream);
     if (e == hipSuccess)
         e = tdes::launch_batch_prefixed(
-            reinterpret_cast<const tdes_msg *>(sl.d_stage + sl.lay.msgs_off), n, sl.d_sched, n,
+            reinterpret_cast<const tdes_msg *>(sl.d_stage + lay.msgs_off), n, sl.d_sched, n,
             nullptr, static_cast<uint8_t *>(s->cfg.d_arena),
-            reinterpret_cast<const uint64_t *>(sl.d_stage + sl.lay.ws_off), sl.stream);
+            reinterpret_cast<const uint64_t *>(sl.d_stage + lay.ws_off), total, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
 }

@@ -20,6 +20,7 @@
 
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 
 #include "bitslice_core.h"
 #include "internal.h"
@@ -271,6 +272,20 @@ struct LaneSlice {
 typedef __attribute__((address_space(3))) volatile uint64_t lds_vu64;
 typedef __attribute__((address_space(3))) volatile uint32_t lds_vu32;
 
+// Messages per mask-table group for a wave spanning n messages: a table of
+// 4 rows if they fit, else of KMAX rows (one pass if they fit; a
+// table builds every one of its rows each round, so fewer rows cost less),
+// else KMAX rows and one pass per KMAX messages.  Most waves of a batch of
+// kilobyte messages span 2 to 5 of them.
+#ifndef TDES_BATCH_ADAPT
+#define TDES_BATCH_ADAPT 1
+#endif
+template <int KMAX>
+__device__ __forceinline__ uint32_t group_rows(uint32_t n) {
+    if (TDES_BATCH_ADAPT && KMAX > 4 && n <= 4) return 4;
+    return KMAX;
+}
+
 template <int KMAX, int WAVES>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
@@ -286,9 +301,9 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
     for (uint64_t base = ((uint64_t)blockIdx.x * kWavesPerBlock + wave) * kWave; base < total;
          base += stride) {
-        // Passes over groups of KMAX consecutive messages of the wave: one
-        // pass unless the wave's 64 slices span more than KMAX messages.
-        uint32_t g0 = 0, n_wave_msgs = 1;
+        // Passes over groups of G consecutive messages of the wave: one pass
+        // unless the wave's 64 slices span more than KMAX messages.
+        uint32_t g0 = 0, n_wave_msgs = 1, G = KMAX;
         do {
             // Issue priority: the message lookup, loads and input transposes
             // at the highest, the rounds at the lowest, so a wave that has
@@ -336,71 +351,82 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
                 const uint64_t left = total - base;
                 const int last = left > (uint64_t)kWave ? kWave - 1 : (int)left - 1;
                 n_wave_msgs = (uint32_t)__builtin_amdgcn_readlane((int)m, last) - lo + 1;
+                G = group_rows<KMAX>(n_wave_msgs);
                 const uint32_t slot = m - lo;
-                const bool mine = active && slot - g0 < (uint32_t)KMAX;
+                const bool mine = active && slot - g0 < G;
                 const tdes_msg d = msgs[m];
                 const uint64_t off = (s - first[m]) * kSlice;
                 *(lds_vu64 *)&mine_ls->src = (uint64_t)(uintptr_t)(in + d.in_off + off);
                 *(lds_vu64 *)&mine_ls->dst = (uint64_t)(uintptr_t)(out + d.out_off + off);
                 *(lds_vu32 *)&mine_ls->nb = mine ? (uint32_t)min((uint64_t)kSlice, d.nbytes - off) : 0u;
-                *(lds_vu32 *)&mine_ls->row = (slot - g0) % KMAX;  // (any row for other groups)
+                *(lds_vu32 *)&mine_ls->row = (slot - g0) & (G - 1);  // (any row for other groups)
                 // lanes 2j, 2j + 1: the two key words of round 0 of the
                 // group's message j (the last one for lanes past the group)
-                const uint32_t kg = min(n_wave_msgs - g0, (uint32_t)KMAX);
+                const uint32_t kg = min(n_wave_msgs - g0, G);
                 const tdes_msg dj = msgs[lo + g0 + min(lane >> 1, kg - 1)];
                 woff = 4u * ((dj.sched_idx < n_sched ? dj.sched_idx : 0u) *
                                  (uint32_t)kDeviceScheduleWords +
                              (dj.dir & 1u) * (uint32_t)kDirWords + (lane & 1u));
                 if (__ballot(mine) == 0) continue;  // a group of empty messages
             }
-            uint32_t h0[32], h1[32];
-            {
-                const uint8_t *src = (const uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->src;
-                const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
+            // load, transposes, the 48 rounds with a table of K rows (K
+            // uniform over the wave), transposes, store: one copy per table
+            // size, so that nothing but a few scalars is live across the choice
+            auto cipher = [&](auto k_rows) {
+                constexpr int K = decltype(k_rows)::value;
+                uint32_t h0[32], h1[32];
+                {
+                    const uint8_t *src = (const uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->src;
+                    const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
 #pragma unroll
-                for (int k = 0; k < 32; k++) {
-                    uint2 v = make_uint2(0u, 0u);
-                    if ((uint32_t)k * 8u < nb) v = *reinterpret_cast<const uint2 *>(src + 8 * k);
-                    h0[k] = v.x;
-                    h1[k] = v.y;
+                    for (int k = 0; k < 32; k++) {
+                        uint2 v = make_uint2(0u, 0u);
+                        if ((uint32_t)k * 8u < nb) v = *reinterpret_cast<const uint2 *>(src + 8 * k);
+                        h0[k] = v.x;
+                        h1[k] = v.y;
+                    }
                 }
-            }
-            TableRounds<KMAX> rr;
-            rr.kg = min(n_wave_msgs - g0, (uint32_t)KMAX);
-            rr.sched = sched;
-            rr.woff = woff;
-            {
-                // entry `lane` of a row: bit eb of the round's word pair (lo,
-                // hi as bits 32..63), found in lane 2j (lo) or 2j + 1 (hi)
-                const uint32_t eb = row_entry_bit((int)lane);
-                rr.sel = 4u * (eb >> 5);
-                rr.bit = eb & 31u;
-            }
-            rr.wr = (lds_u32 *)tables[wave] + lane;
-            rr.p0 = (const lds_u32 *)tables[wave] + *(lds_vu32 *)&mine_ls->row * kRowWords;
-            transpose32(h0);
-            __builtin_amdgcn_sched_barrier(0);
-            transpose32(h1);
-            pin_words(h0);
-            pin_words(h1);
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_setprio(0);
-            des3_planes(h0, h1, rr);
-            __builtin_amdgcn_sched_barrier(0);
-            transpose32(h0);
-            __builtin_amdgcn_sched_barrier(0);
-            transpose32(h1);
-            pin_words(h0);
-            pin_words(h1);
-            {
-                uint8_t *dst = (uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->dst;
-                const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
+                TableRounds<K> rr;
+                rr.kg = min(n_wave_msgs - g0, (uint32_t)K);
+                rr.sched = sched;
+                rr.woff = woff;
+                {
+                    // entry `lane` of a row: bit eb of the round's word pair
+                    // (lo, hi as bits 32..63), found in lane 2j (lo) or 2j + 1 (hi)
+                    const uint32_t eb = row_entry_bit((int)lane);
+                    rr.sel = 4u * (eb >> 5);
+                    rr.bit = eb & 31u;
+                }
+                rr.wr = (lds_u32 *)tables[wave] + lane;
+                rr.p0 = (const lds_u32 *)tables[wave] + *(lds_vu32 *)&mine_ls->row * kRowWords;
+                transpose32(h0);
+                __builtin_amdgcn_sched_barrier(0);
+                transpose32(h1);
+                pin_words(h0);
+                pin_words(h1);
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(0);
+                des3_planes(h0, h1, rr);
+                __builtin_amdgcn_sched_barrier(0);
+                transpose32(h0);
+                __builtin_amdgcn_sched_barrier(0);
+                transpose32(h1);
+                pin_words(h0);
+                pin_words(h1);
+                {
+                    uint8_t *dst = (uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->dst;
+                    const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
 #pragma unroll
-                for (int k = 0; k < 32; k++)
-                    if ((uint32_t)k * 8u < nb)
-                        *reinterpret_cast<uint2 *>(dst + 8 * k) = make_uint2(h0[k], h1[k]);
-            }
-        } while ((g0 += KMAX) < n_wave_msgs);
+                    for (int k = 0; k < 32; k++)
+                        if ((uint32_t)k * 8u < nb)
+                            *reinterpret_cast<uint2 *>(dst + 8 * k) = make_uint2(h0[k], h1[k]);
+                }
+            };
+            if (KMAX > 4 && G == 4)
+                cipher(std::integral_constant<int, (KMAX > 4 ? 4 : KMAX)>{});
+            else
+                cipher(std::integral_constant<int, KMAX>{});
+        } while ((g0 += G) < n_wave_msgs);
     }
 }
 

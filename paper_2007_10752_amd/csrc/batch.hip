@@ -31,7 +31,7 @@
 // the occupancy the register budget is set for.  The first is the default
 // (with a grid of twice the resident workgroups); tdes_batch_autotune picks
 // among all of them and grids of 1..4 times the resident workgroups.
-#define TDES_BATCH_VARIANTS(X) X(8, 4) X(4, 4) X(16, 4) X(8, 3) X(4, 3) X(16, 3)
+#define TDES_BATCH_VARIANTS(X) X(8, 4) X(4, 4) X(16, 4) X(8, 3) X(4, 3) X(16, 3) X(8, 5) X(4, 5)
 
 namespace tdes {
 
@@ -167,7 +167,7 @@ __device__ __forceinline__ uint32_t row_entry_bit(int lane) {
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-template <int KMAX>
+template <int KMAX, int PIPE = TDES_BS_PIPE>
 struct TableRounds {
     lds_u32 *wr;          // this wave's table + lane: where this lane writes
     const lds_u32 *p0;    // this lane's row in round buffer 0 (buffer 1 follows)
@@ -217,7 +217,7 @@ struct TableRounds {
         build<0>();
         fetch(1);
 #pragma unroll
-        for (int j = 0; j < TDES_BS_PIPE; j++) LdsBoxLoad{}(pm[j], p0 + kBsBoxMasks * j, BS_BOX_NDUP[j]);
+        for (int j = 0; j < PIPE; j++) LdsBoxLoad{}(pm[j], p0 + kBsBoxMasks * j, BS_BOX_NDUP[j]);
     }
     template <int PH>
     __device__ __forceinline__ void round(uint32_t (&d)[32], const uint32_t (&r)[32], int t) {
@@ -227,7 +227,7 @@ struct TableRounds {
         // into buffer 0, which the rounds no longer read.
         build<PH ^ 1>();
         fetch(t + 2);
-        bs_round_piped<TDES_BS_PIPE>(d, r, p0 + PH * kBuf, p0 + (PH ^ 1) * kBuf, pm, LdsBoxLoad{});
+        bs_round_piped<PIPE>(d, r, p0 + PH * kBuf, p0 + (PH ^ 1) * kBuf, pm, LdsBoxLoad{});
     }
     // XOR extra mask group g (word 96 + g of each message) into a: expanded
     // into a buffer the rounds are not using (buffer 1 between passes,
@@ -271,6 +271,15 @@ struct LaneSlice {
 };
 typedef __attribute__((address_space(3))) volatile uint64_t lds_vu64;
 typedef __attribute__((address_space(3))) volatile uint32_t lds_vu32;
+// Global-memory views of a lane's slice (its addresses come through LDS as
+// integers): 16-byte accesses at 8-byte alignment (message offsets are only
+// multiples of 8) and 8-byte accesses.
+typedef uint32_t v4u_a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef __attribute__((address_space(1))) const v4u_a8 g_cu4;
+typedef __attribute__((address_space(1))) v4u_a8 g_u4;
+typedef __attribute__((address_space(1))) const v2u g_cu2;
+typedef __attribute__((address_space(1))) v2u g_u2;
+constexpr int kBufferFlags = 0x00020000;  // buffer resource word 3 for raw loads and stores
 
 // Messages per mask-table group for a wave spanning n messages: a table of
 // 4 rows if they fit, else of KMAX rows (one pass if they fit; a
@@ -280,6 +289,15 @@ typedef __attribute__((address_space(3))) volatile uint32_t lds_vu32;
 #ifndef TDES_BATCH_ADAPT
 #define TDES_BATCH_ADAPT 1
 #endif
+// Lane 0's value of a 64-bit integer, in scalar registers.  (readfirstlane
+// returns int: each half goes through uint32_t so that the low half is not
+// sign-extended into the high one.)
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <int KMAX>
 __device__ __forceinline__ uint32_t group_rows(uint32_t n) {
     if (TDES_BATCH_ADAPT && KMAX > 4 && n <= 4) return 4;
@@ -304,6 +322,11 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
         // Passes over groups of G consecutive messages of the wave: one pass
         // unless the wave's 64 slices span more than KMAX messages.
         uint32_t g0 = 0, n_wave_msgs = 1, G = KMAX;
+        // a wave whose slices all lie in one message: the message's bytes
+        // from lane 0's slice on (wave-uniform), read and written like the
+        // plain kernel's chunk (0: the wave spans several messages)
+        uint32_t one_avail = 0;
+        uint64_t one_src = 0, one_dst = 0;
         do {
             // Issue priority: the message lookup, loads and input transposes
             // at the highest, the rounds at the lowest, so a wave that has
@@ -356,6 +379,18 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
                 const bool mine = active && slot - g0 < G;
                 const tdes_msg d = msgs[m];
                 const uint64_t off = (s - first[m]) * kSlice;
+                one_avail = 0;
+                if (n_wave_msgs == 1) {
+                    // lane 0 is active (base < total) and its slice is the
+                    // wave's first; the active lanes' slices follow it
+                    const uint64_t rem = d.nbytes - off;
+                    one_avail = __builtin_amdgcn_readfirstlane(
+                        (uint32_t)(rem < (uint64_t)kWave * kSlice ? rem : (uint64_t)kWave * kSlice));
+                    const uint64_t a = (uint64_t)(uintptr_t)(in + d.in_off + off);
+                    const uint64_t b = (uint64_t)(uintptr_t)(out + d.out_off + off);
+                    one_src = uniform_u64(a);
+                    one_dst = uniform_u64(b);
+                }
                 *(lds_vu64 *)&mine_ls->src = (uint64_t)(uintptr_t)(in + d.in_off + off);
                 *(lds_vu64 *)&mine_ls->dst = (uint64_t)(uintptr_t)(out + d.out_off + off);
                 *(lds_vu32 *)&mine_ls->nb = mine ? (uint32_t)min((uint64_t)kSlice, d.nbytes - off) : 0u;
@@ -375,18 +410,50 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
             auto cipher = [&](auto k_rows) {
                 constexpr int K = decltype(k_rows)::value;
                 uint32_t h0[32], h1[32];
-                {
-                    const uint8_t *src = (const uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->src;
+                const uint32_t lane_off = lane * 16u;
+                if (one_avail != 0) {
+                    // one message: coalesced as in the plain kernel (lane l
+                    // takes the 16-byte pieces at l * 16 + k * 1024), through
+                    // a buffer resource sized to the bytes left in the
+                    // message, whose range check zero-fills past its end
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        (void *)(uintptr_t)one_src, 0, (int)one_avail, kBufferFlags);
+#pragma unroll
+                    for (int k = 0; k < 16; k++) {
+                        const v2u a = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, k * 1024, 0);
+                        const v2u b = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off + 8u, k * 1024, 0);
+                        h0[2 * k] = a[0];
+                        h1[2 * k] = a[1];
+                        h0[2 * k + 1] = b[0];
+                        h1[2 * k + 1] = b[1];
+                    }
+                } else {
+                    // own slice, 16 bytes at a time at min(16 k, nb - 16): a
+                    // piece past the slice's last block repeats the last
+                    // pieces, and the store below writes it back to the same
+                    // place with the same (deterministic) result, so no
+                    // access leaves the slice and none needs a branch
+                    const uint64_t src = *(lds_vu64 *)&mine_ls->src;
                     const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
 #pragma unroll
-                    for (int k = 0; k < 32; k++) {
-                        uint2 v = make_uint2(0u, 0u);
-                        if ((uint32_t)k * 8u < nb) v = *reinterpret_cast<const uint2 *>(src + 8 * k);
-                        h0[k] = v.x;
-                        h1[k] = v.y;
+                    for (int k = 0; k < 32; k++) h0[k] = h1[k] = 0;
+                    if (nb >= 16) {
+#pragma unroll
+                        for (int k = 0; k < 16; k++) {
+                            const uint32_t o = min(16u * (uint32_t)k, nb - 16u);
+                            const v4u v = *(g_cu4 *)(uintptr_t)(src + o);
+                            h0[2 * k] = v[0];
+                            h1[2 * k] = v[1];
+                            h0[2 * k + 1] = v[2];
+                            h1[2 * k + 1] = v[3];
+                        }
+                    } else if (nb == 8) {
+                        const v2u v = *(g_cu2 *)(uintptr_t)src;
+                        h0[0] = v[0];
+                        h1[0] = v[1];
                     }
                 }
-                TableRounds<K> rr;
+                TableRounds<K, (WAVES >= 5 ? 1 : TDES_BS_PIPE)> rr;
                 rr.kg = min(n_wave_msgs - g0, (uint32_t)K);
                 rr.sched = sched;
                 rr.woff = woff;
@@ -413,13 +480,29 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
                 transpose32(h1);
                 pin_words(h0);
                 pin_words(h1);
-                {
-                    uint8_t *dst = (uint8_t *)(uintptr_t)*(lds_vu64 *)&mine_ls->dst;
-                    const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
+                if (one_avail != 0) {
+                    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+                        (void *)(uintptr_t)one_dst, 0, (int)one_avail, kBufferFlags);
 #pragma unroll
-                    for (int k = 0; k < 32; k++)
-                        if ((uint32_t)k * 8u < nb)
-                            *reinterpret_cast<uint2 *>(dst + 8 * k) = make_uint2(h0[k], h1[k]);
+                    for (int k = 0; k < 16; k++) {
+                        __builtin_amdgcn_raw_buffer_store_b64(v2u{h0[2 * k], h1[2 * k]}, rd, lane_off,
+                                                              k * 1024, 0);
+                        __builtin_amdgcn_raw_buffer_store_b64(v2u{h0[2 * k + 1], h1[2 * k + 1]}, rd,
+                                                              lane_off + 8u, k * 1024, 0);
+                    }
+                } else {
+                    const uint64_t dst = *(lds_vu64 *)&mine_ls->dst;
+                    const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
+                    if (nb >= 16) {
+#pragma unroll
+                        for (int k = 0; k < 16; k++) {
+                            const uint32_t o = min(16u * (uint32_t)k, nb - 16u);
+                            *(g_u4 *)(uintptr_t)(dst + o) =
+                                v4u_a8{h0[2 * k], h1[2 * k], h0[2 * k + 1], h1[2 * k + 1]};
+                        }
+                    } else if (nb == 8) {
+                        *(g_u2 *)(uintptr_t)dst = v2u{h0[0], h1[0]};
+                    }
                 }
             };
             if (KMAX > 4 && G == 4)

@@ -92,6 +92,49 @@ def test_in_place_and_gaps(torch_dev):
         assert np.array_equal(got[gseg], data[gseg]), "gap bytes were written"
 
 
+def test_single_message_waves(torch_dev):
+    # Waves whose 64 slices lie in one message take the coalesced path
+    # (buffer resource sized to the bytes left in the message); the others
+    # read their slices 16 bytes at a time, clamped to the slice.  Messages
+    # of whole waves, of a wave plus 8 bytes, of odd block counts and of one
+    # block, at offsets that are multiples of 8 but not of 16, both in one
+    # batch and each alone (then every wave of it is single-message).
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x305)
+    lengths = np.array([16384, 16392, 3 * 16384 + 8, (1 << 20) + 8, 8, 264, 40, 16, 24,
+                        2 * 16384 - 8], dtype=np.int64)
+    n = len(lengths)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    gap = 8
+    offs = np.zeros(n, dtype=np.int64)
+    offs[1:] = np.cumsum(lengths + gap)[:-1]
+    offs += 8  # 8-byte aligned, not 16-byte aligned
+    total = int(offs[-1] + lengths[-1] + 8)
+    data = W.uniform_bytes(g, total)
+    x = torch.from_numpy(data).cuda()
+    want = data.copy()
+    for i in range(n):
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        want[seg] = oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))
+    _say("batch single-message waves", n, total)
+    out = x.clone()
+    T.Batch(keys, offs, offs, lengths, dirs).submit(x, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    for i in range(n):
+        out = x.clone()
+        T.Batch(keys[i:i + 1], offs[i:i + 1], offs[i:i + 1], lengths[i:i + 1],
+                dirs[i:i + 1]).submit(x, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(got[seg], want[seg]), i
+        rest = np.ones(total, dtype=bool)
+        rest[seg] = False
+        assert np.array_equal(got[rest], data[rest]), ("bytes outside the message changed", i)
+
+
 def test_invalid_messages_are_skipped(torch_dev):
     torch = torch_dev
     g = W.rng(W.SEED_BASE + 0x302)

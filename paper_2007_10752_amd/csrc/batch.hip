@@ -264,10 +264,17 @@ struct TableRounds {
 // A lane's slice between the lookup and the cipher phases of a pass: kept in
 // LDS (volatile, so the compiler cannot forward it in registers), so that
 // nothing of the lookup stays in registers through the rounds.
+// The lanes of a wave that hold slices of one message form a run; the run
+// reads and writes its message's bytes together, coalesced: lane i of a run
+// of L lanes takes the 16-byte pieces at i * 16 + k * 16 L (k = 0..15) of
+// the run's bytes, as the plain kernel does with a whole wave (one key per
+// run, so any assignment of the run's blocks to its lanes is ECB).
 struct LaneSlice {
-    uint64_t src, dst;  // device addresses of the lane's 256-byte slice
-    uint32_t nb;        // bytes of it in the message (0: no work for this lane)
+    uint64_t src, dst;  // device addresses of the lane's run (its message's bytes in this wave)
+    uint32_t nb;        // bytes of the run (0: no work for this lane)
     uint32_t row;       // this lane's row of the mask table
+    uint32_t pos;       // byte offset of this lane's first piece in the run: 16 i
+    uint32_t stride;    // bytes between its pieces: 16 L
 };
 typedef __attribute__((address_space(3))) volatile uint64_t lds_vu64;
 typedef __attribute__((address_space(3))) volatile uint32_t lds_vu32;
@@ -279,7 +286,6 @@ typedef __attribute__((address_space(1))) const v4u_a8 g_cu4;
 typedef __attribute__((address_space(1))) v4u_a8 g_u4;
 typedef __attribute__((address_space(1))) const v2u g_cu2;
 typedef __attribute__((address_space(1))) v2u g_u2;
-constexpr int kBufferFlags = 0x00020000;  // buffer resource word 3 for raw loads and stores
 
 // Messages per mask-table group for a wave spanning n messages: a table of
 // 4 rows if they fit, else of KMAX rows (one pass if they fit; a
@@ -289,15 +295,6 @@ constexpr int kBufferFlags = 0x00020000;  // buffer resource word 3 for raw load
 #ifndef TDES_BATCH_ADAPT
 #define TDES_BATCH_ADAPT 1
 #endif
-// Lane 0's value of a 64-bit integer, in scalar registers.  (readfirstlane
-// returns int: each half goes through uint32_t so that the low half is not
-// sign-extended into the high one.)
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 template <int KMAX>
 __device__ __forceinline__ uint32_t group_rows(uint32_t n) {
     if (TDES_BATCH_ADAPT && KMAX > 4 && n <= 4) return 4;
@@ -322,11 +319,6 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
         // Passes over groups of G consecutive messages of the wave: one pass
         // unless the wave's 64 slices span more than KMAX messages.
         uint32_t g0 = 0, n_wave_msgs = 1, G = KMAX;
-        // a wave whose slices all lie in one message: the message's bytes
-        // from lane 0's slice on (wave-uniform), read and written like the
-        // plain kernel's chunk (0: the wave spans several messages)
-        uint32_t one_avail = 0;
-        uint64_t one_src = 0, one_dst = 0;
         do {
             // Issue priority: the message lookup, loads and input transposes
             // at the highest, the rounds at the lowest, so a wave that has
@@ -378,22 +370,18 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
                 const uint32_t slot = m - lo;
                 const bool mine = active && slot - g0 < G;
                 const tdes_msg d = msgs[m];
-                const uint64_t off = (s - first[m]) * kSlice;
-                one_avail = 0;
-                if (n_wave_msgs == 1) {
-                    // lane 0 is active (base < total) and its slice is the
-                    // wave's first; the active lanes' slices follow it
-                    const uint64_t rem = d.nbytes - off;
-                    one_avail = __builtin_amdgcn_readfirstlane(
-                        (uint32_t)(rem < (uint64_t)kWave * kSlice ? rem : (uint64_t)kWave * kSlice));
-                    const uint64_t a = (uint64_t)(uintptr_t)(in + d.in_off + off);
-                    const uint64_t b = (uint64_t)(uintptr_t)(out + d.out_off + off);
-                    one_src = uniform_u64(a);
-                    one_dst = uniform_u64(b);
-                }
-                *(lds_vu64 *)&mine_ls->src = (uint64_t)(uintptr_t)(in + d.in_off + off);
-                *(lds_vu64 *)&mine_ls->dst = (uint64_t)(uintptr_t)(out + d.out_off + off);
-                *(lds_vu32 *)&mine_ls->nb = mine ? (uint32_t)min((uint64_t)kSlice, d.nbytes - off) : 0u;
+                // this lane's run: the slices of message m in this wave
+                const uint64_t f0 = first[m], f1 = first[m + 1];
+                const uint64_t run0 = f0 > base ? f0 : base;
+                const uint64_t run1 = f1 < base + kWave ? f1 : base + kWave;
+                const uint64_t run_off = (run0 - f0) * kSlice;  // in the message
+                const uint64_t run_len = (run1 - run0) * kSlice;
+                const uint64_t rem = d.nbytes - run_off;
+                *(lds_vu64 *)&mine_ls->src = (uint64_t)(uintptr_t)(in + d.in_off + run_off);
+                *(lds_vu64 *)&mine_ls->dst = (uint64_t)(uintptr_t)(out + d.out_off + run_off);
+                *(lds_vu32 *)&mine_ls->nb = mine ? (uint32_t)(rem < run_len ? rem : run_len) : 0u;
+                *(lds_vu32 *)&mine_ls->pos = (uint32_t)(s - run0) * 16u;
+                *(lds_vu32 *)&mine_ls->stride = (uint32_t)(run1 - run0) * 16u;
                 *(lds_vu32 *)&mine_ls->row = (slot - g0) & (G - 1);  // (any row for other groups)
                 // lanes 2j, 2j + 1: the two key words of round 0 of the
                 // group's message j (the last one for lanes past the group)
@@ -410,44 +398,29 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
             auto cipher = [&](auto k_rows) {
                 constexpr int K = decltype(k_rows)::value;
                 uint32_t h0[32], h1[32];
-                const uint32_t lane_off = lane * 16u;
-                if (one_avail != 0) {
-                    // one message: coalesced as in the plain kernel (lane l
-                    // takes the 16-byte pieces at l * 16 + k * 1024), through
-                    // a buffer resource sized to the bytes left in the
-                    // message, whose range check zero-fills past its end
-                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                        (void *)(uintptr_t)one_src, 0, (int)one_avail, kBufferFlags);
-#pragma unroll
-                    for (int k = 0; k < 16; k++) {
-                        const v2u a = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, k * 1024, 0);
-                        const v2u b = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off + 8u, k * 1024, 0);
-                        h0[2 * k] = a[0];
-                        h1[2 * k] = a[1];
-                        h0[2 * k + 1] = b[0];
-                        h1[2 * k + 1] = b[1];
-                    }
-                } else {
-                    // own slice, 16 bytes at a time at min(16 k, nb - 16): a
-                    // piece past the slice's last block repeats the last
-                    // pieces, and the store below writes it back to the same
-                    // place with the same (deterministic) result, so no
-                    // access leaves the slice and none needs a branch
+                {
+                    // the run's piece k for this lane, at min(pos + k stride,
+                    // nb - 16): pieces past the run's last block repeat its
+                    // last pieces and are written back to the same place
+                    // with the same (deterministic) result, so no access
+                    // leaves the run and none needs a branch
                     const uint64_t src = *(lds_vu64 *)&mine_ls->src;
                     const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
+                    const uint32_t pos = *(lds_vu32 *)&mine_ls->pos;
+                    const uint32_t stride = *(lds_vu32 *)&mine_ls->stride;
 #pragma unroll
                     for (int k = 0; k < 32; k++) h0[k] = h1[k] = 0;
                     if (nb >= 16) {
 #pragma unroll
                         for (int k = 0; k < 16; k++) {
-                            const uint32_t o = min(16u * (uint32_t)k, nb - 16u);
+                            const uint32_t o = min(pos + (uint32_t)k * stride, nb - 16u);
                             const v4u v = *(g_cu4 *)(uintptr_t)(src + o);
                             h0[2 * k] = v[0];
                             h1[2 * k] = v[1];
                             h0[2 * k + 1] = v[2];
                             h1[2 * k + 1] = v[3];
                         }
-                    } else if (nb == 8) {
+                    } else if (nb == 8) {  // a run of one block
                         const v2u v = *(g_cu2 *)(uintptr_t)src;
                         h0[0] = v[0];
                         h1[0] = v[1];
@@ -480,23 +453,15 @@ void batch_bitslice_kernel(const tdes_msg *__restrict__ msgs, uint32_t n_msgs,
                 transpose32(h1);
                 pin_words(h0);
                 pin_words(h1);
-                if (one_avail != 0) {
-                    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
-                        (void *)(uintptr_t)one_dst, 0, (int)one_avail, kBufferFlags);
-#pragma unroll
-                    for (int k = 0; k < 16; k++) {
-                        __builtin_amdgcn_raw_buffer_store_b64(v2u{h0[2 * k], h1[2 * k]}, rd, lane_off,
-                                                              k * 1024, 0);
-                        __builtin_amdgcn_raw_buffer_store_b64(v2u{h0[2 * k + 1], h1[2 * k + 1]}, rd,
-                                                              lane_off + 8u, k * 1024, 0);
-                    }
-                } else {
+                {
                     const uint64_t dst = *(lds_vu64 *)&mine_ls->dst;
                     const uint32_t nb = *(lds_vu32 *)&mine_ls->nb;
+                    const uint32_t pos = *(lds_vu32 *)&mine_ls->pos;
+                    const uint32_t stride = *(lds_vu32 *)&mine_ls->stride;
                     if (nb >= 16) {
 #pragma unroll
                         for (int k = 0; k < 16; k++) {
-                            const uint32_t o = min(16u * (uint32_t)k, nb - 16u);
+                            const uint32_t o = min(pos + (uint32_t)k * stride, nb - 16u);
                             *(g_u4 *)(uintptr_t)(dst + o) =
                                 v4u_a8{h0[2 * k], h1[2 * k], h0[2 * k + 1], h1[2 * k + 1]};
                         }

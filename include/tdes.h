@@ -196,7 +196,7 @@ tdes_status tdes_batch_submit(const tdes_msg *d_msgs, size_t n_msgs, const void 
  * for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc).  The
  * descriptor scan's table lives in a fixed array in the library's device
- * memory (8 MiB + 24 bytes: room for TDES_BATCH_NOALLOC_MAX_MSGS messages),
+ * memory (8 MiB + 16 KiB + 24 bytes: room for TDES_BATCH_NOALLOC_MAX_MSGS messages),
  * one per device, held until the process ends; its address is looked up on
  * the first call on each device.  Nothing in it must start at zero: the
  * scan rewrites what the cipher reads on every call.  Every call on a device
@@ -274,7 +274,8 @@ typedef struct {
                            table (4, 8 or 16; a wave over more messages takes
                            one pass per group)                              */
     uint32_t waves;     /* waves per SIMD the variant's register budget is
-                           set for (3 or 4)                                 */
+                           set for.  Compiled: {4, 8} x {3, 4, 5} and
+                           {16, 3}                                          */
     uint32_t grid_mult; /* grid = grid_mult x the workgroups that fit at
                            once (1..4)                                      */
     uint32_t saved;     /* output of tdes_batch_autotune: 1 if the result was

@@ -28,10 +28,10 @@
 
 // The compiled variants of the batched cipher, X(KMAX, WAVES): KMAX
 // messages per wave pass share the LDS mask table; WAVES waves per SIMD is
-// the occupancy the register budget is set for.  The first is the default
+// the occupancy the register budget is set for (KMAX 16 does not fit 4).  The first is the default
 // (with a grid of twice the resident workgroups); tdes_batch_autotune picks
 // among all of them and grids of 1..4 times the resident workgroups.
-#define TDES_BATCH_VARIANTS(X) X(8, 4) X(4, 4) X(16, 4) X(8, 3) X(4, 3) X(16, 3) X(8, 5) X(4, 5)
+#define TDES_BATCH_VARIANTS(X) X(8, 4) X(4, 4) X(8, 3) X(4, 3) X(16, 3) X(8, 5) X(4, 5)
 
 namespace tdes {
 
@@ -74,63 +74,80 @@ __device__ __forceinline__ uint64_t wave_scan(uint64_t v, int lane) {
     return v;
 }
 
-// One workgroup scans the descriptors in chunks of 16 x 512: wave w owns
-// descriptors w*512 .. w*512 + 511 of the chunk and walks them 64 at a time
-// (coalesced loads, issued together: the index is clamped and the result
-// masked so no load sits under a branch), scanning each step with shuffles
-// and carrying its own running total; one barrier then gives every wave the
-// totals of the waves before it, and the first slices are written
-// (coalesced).  Larger batches loop over chunks, carrying the running total.
-constexpr int kScanSteps = 8;  // 64-descriptor steps per wave and chunk
+// The descriptor scan over many workgroups: each tile of kTile descriptors
+// is validated and scanned by its own workgroup (tile-local prefixes, the
+// tile's total and bad count); then every tile adds the total of the tiles
+// before it (one launch that sums them per workgroup up to kFusedTiles
+// tiles; beyond, one workgroup scans the tiles' totals into offsets and a
+// third launch adds them).  A single workgroup scanning all
+// descriptors was bound by one CU's loads (16,384 descriptors: ~17 us).
+// Workspace words past the first-slice table: T tile totals (then offsets)
+// and T tile bad counts, T = ceil(n / kTile).
+constexpr int kTile = kScanThreads;
 
-__global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg *msgs, size_t n,
-                                                                 size_t n_sched, BatchBounds bb,
-                                                                 uint64_t *ws,
-                                                                 uint64_t *skipped_out) {
+__device__ __forceinline__ size_t tile_count(size_t n) { return (n + kTile - 1) / kTile; }
+
+__global__ __launch_bounds__(kScanThreads) void batch_tile_scan_kernel(const tdes_msg *msgs, size_t n,
+                                                                      size_t n_sched, BatchBounds bb,
+                                                                      uint64_t *ws) {
     constexpr int kWaves = kScanThreads / kWave;
-    constexpr size_t kWaveMsgs = (size_t)kWave * kScanSteps;
-    constexpr size_t kChunkMsgs = kWaveMsgs * kWaves;
     __shared__ uint64_t wave_tot[kWaves];
     __shared__ uint32_t wave_bad[kWaves];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const size_t i = (size_t)blockIdx.x * kTile + threadIdx.x;
+    const bool live = i < n;
+    const tdes_msg m = msgs[live ? i : n - 1];
+    bool bad = false;
+    const uint64_t vi = slices_of(m, n_sched, bb, &bad);
+    const uint64_t v = live ? vi : 0;
+    const uint64_t incl = wave_scan(v, lane);
+    const uint32_t nbad = (uint32_t)__popcll(__ballot(live && bad));
+    if (lane == kWave - 1) wave_tot[w] = incl;
+    if (lane == 0) wave_bad[w] = nbad;
+    __syncthreads();
+    uint64_t before = 0, tile = 0, tile_bad = 0;
+    for (int k = 0; k < kWaves; k++) {
+        before += k < w ? wave_tot[k] : 0;
+        tile += wave_tot[k];
+        tile_bad += wave_bad[k];
+    }
+    if (live) ws[kWsHeader + i] = before + incl - v;  // within the tile
+    if (threadIdx.x == 0) {
+        uint64_t *tiles = ws + kWsHeader + n + 1;
+        tiles[blockIdx.x] = tile;
+        tiles[tile_count(n) + blockIdx.x] = tile_bad;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void batch_tile_offsets_kernel(size_t n, uint64_t *ws,
+                                                                         uint64_t *skipped_out) {
+    constexpr int kWaves = kScanThreads / kWave;
+    __shared__ uint64_t wave_tot[kWaves];
+    __shared__ uint64_t wave_bad[kWaves];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const size_t T = tile_count(n);
+    uint64_t *tiles = ws + kWsHeader + n + 1;
     uint64_t run = 0, bad_total = 0;
-    for (size_t base = 0; base < n; base += kChunkMsgs) {
-        const size_t wbase = base + (size_t)w * kWaveMsgs;
-        uint64_t pre[kScanSteps];  // exclusive prefix within the wave's range
-        uint64_t carry = 0;
-        uint32_t nbad = 0;
+    for (size_t base = 0; base < T; base += kScanThreads) {
+        const size_t t = base + threadIdx.x;
+        const uint64_t v = t < T ? tiles[t] : 0;
+        const uint64_t b = t < T ? tiles[T + t] : 0;
+        const uint64_t incl = wave_scan(v, lane);
+        uint64_t bsum = b;
 #pragma unroll
-        for (int k = 0; k < kScanSteps; k++) {
-            const size_t i = wbase + (size_t)k * kWave + lane;
-            const tdes_msg m = msgs[i < n ? i : n - 1];
-            bool bad = false;
-            const uint64_t vi = slices_of(m, n_sched, bb, &bad);
-            const uint64_t v = i < n ? vi : 0;
-            nbad += (bad && i < n) ? 1u : 0u;
-            const uint64_t incl = wave_scan(v, lane);
-            pre[k] = carry + incl - v;
-            carry += __shfl(incl, kWave - 1, kWave);
-        }
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) nbad += __shfl_xor(nbad, d, kWave);
-        if (lane == 0) {
-            wave_tot[w] = carry;
-            wave_bad[w] = nbad;
-        }
+        for (int d = 1; d < kWave; d <<= 1) bsum += __shfl_xor(bsum, d, kWave);
+        if (lane == kWave - 1) wave_tot[w] = incl;
+        if (lane == 0) wave_bad[w] = bsum;
         __syncthreads();
-        uint64_t before = 0, tile = 0, tile_bad = 0;
+        uint64_t before = 0, chunk = 0, chunk_bad = 0;
         for (int k = 0; k < kWaves; k++) {
             before += k < w ? wave_tot[k] : 0;
-            tile += wave_tot[k];
-            tile_bad += wave_bad[k];
+            chunk += wave_tot[k];
+            chunk_bad += wave_bad[k];
         }
-#pragma unroll
-        for (int k = 0; k < kScanSteps; k++) {
-            const size_t i = wbase + (size_t)k * kWave + lane;
-            if (i < n) ws[kWsHeader + i] = run + before + pre[k];
-        }
-        run += tile;
-        bad_total += tile_bad;
+        if (t < T) tiles[t] = run + before + incl - v;  // the tile's offset
+        run += chunk;
+        bad_total += chunk_bad;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -138,6 +155,55 @@ __global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const tdes_msg
         ws[1] = bad_total;
         ws[kWsHeader + n] = run;
         if (skipped_out != nullptr) *skipped_out = bad_total;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void batch_tile_add_kernel(size_t n, uint64_t *ws) {
+    if (blockIdx.x == 0) return;  // the first tile's offset is 0
+    const size_t i = (size_t)blockIdx.x * kTile + threadIdx.x;
+    const uint64_t off = ws[kWsHeader + n + 1 + blockIdx.x];
+    if (i < n) ws[kWsHeader + i] += off;
+}
+
+// Tile offsets and their addition in one launch, for batches of at most
+// kFusedTiles tiles: workgroup b sums the totals of tiles 0..b-1 itself (one
+// load per thread per 1024 tiles) and adds the sum to its tile's entries;
+// the last workgroup also writes the batch's total and skipped count.
+constexpr size_t kFusedTiles = 8192;
+
+__device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t *red) {
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    uint64_t s = 0;
+    for (int k = 0; k < kScanThreads / kWave; k++) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kScanThreads) void batch_tile_finish_kernel(size_t n, uint64_t *ws,
+                                                                        uint64_t *skipped_out) {
+    __shared__ uint64_t red[kScanThreads / kWave];
+    const size_t T = tile_count(n), b = blockIdx.x;
+    const uint64_t *tiles = ws + kWsHeader + n + 1;
+    uint64_t part = 0;
+    for (size_t t = threadIdx.x; t < b; t += kScanThreads) part += tiles[t];
+    const uint64_t off = block_sum(part, red);
+    const size_t i = b * kTile + threadIdx.x;
+    if (i < n && off != 0) ws[kWsHeader + i] += off;
+    if (b == T - 1) {
+        uint64_t bad = 0;
+        for (size_t t = threadIdx.x; t < T; t += kScanThreads) bad += tiles[T + t];
+        bad = block_sum(bad, red);
+        if (threadIdx.x == 0) {
+            const uint64_t total = off + tiles[b];
+            ws[0] = total;
+            ws[1] = bad;
+            ws[kWsHeader + n] = total;
+            if (skipped_out != nullptr) *skipped_out = bad;
+        }
     }
 }
 
@@ -680,14 +746,18 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
     return e;
 }
 
-size_t batch_workspace_bytes(size_t n_msgs) { return (kWsHeader + n_msgs + 1) * sizeof(uint64_t); }
+size_t batch_workspace_bytes(size_t n_msgs) {
+    const size_t tiles = (n_msgs + kTile - 1) / kTile;
+    return (kWsHeader + n_msgs + 1 + 2 * tiles) * sizeof(uint64_t);
+}
 
 // The workspace of the no-allocation entry point: a fixed array in device
 // memory (each device holds its own copy), sized for TDES_BATCH_NOALLOC_MAX_MSGS
 // messages.  In host code its name is not a device address; the address is
 // looked up once per device (with that device current) and kept.
 static_assert(TDES_BATCH_NOALLOC_MAX_MSGS <= TDES_BATCH_MAX_MSGS, "no-alloc limit");
-constexpr size_t kNoAllocWords = kWsHeader + (size_t)TDES_BATCH_NOALLOC_MAX_MSGS + 1;
+constexpr size_t kNoAllocWords = kWsHeader + (size_t)TDES_BATCH_NOALLOC_MAX_MSGS + 1 +
+                                 2 * (((size_t)TDES_BATCH_NOALLOC_MAX_MSGS + kTile - 1) / kTile);
 static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
 
 hipError_t noalloc_workspace(uint64_t **ws, size_t *ws_bytes) {
@@ -719,9 +789,24 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
                         size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
                         uint64_t out_bytes, uint64_t *ws, uint64_t *skipped_out,
                         hipStream_t stream) {
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, msgs, n_msgs,
-                       n_schedules, BatchBounds{in_bytes, out_bytes}, ws, skipped_out);
+    const size_t T = (n_msgs + kTile - 1) / kTile;  // n_msgs >= 1
+    if (T > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_tile_scan_kernel, dim3((unsigned)T), dim3(kScanThreads), 0, stream,
+                       msgs, n_msgs, n_schedules, BatchBounds{in_bytes, out_bytes}, ws);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (T <= kFusedTiles) {
+        hipLaunchKernelGGL(batch_tile_finish_kernel, dim3((unsigned)T), dim3(kScanThreads), 0,
+                           stream, n_msgs, ws, skipped_out);
+    } else {
+        hipLaunchKernelGGL(batch_tile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, stream,
+                           n_msgs, ws, skipped_out);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(batch_tile_add_kernel, dim3((unsigned)T), dim3(kScanThreads), 0, stream,
+                           n_msgs, ws);
+    }
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_cipher(msgs, n_msgs, schedules, n_schedules, in, out, ws, 0, stream);
 }

@@ -183,11 +183,13 @@ def test_16k_lognormal_batch(torch_dev):
         assert np.array_equal(got[o:o + n], want), i
 
 
-@pytest.mark.parametrize("n", [1, 8191, 8192, 8193, 20000])
+@pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 8191, 8192, 8193, 20000])
 def test_scan_chunk_boundaries(torch_dev, n):
-    # The descriptor scan works in chunks of 8192 messages: batches just
-    # below, at and just above a chunk edge, and one spanning three chunks,
-    # with short messages (one to three slices) and some empty ones.
+    # The descriptor scan works in tiles of 1024 messages (one workgroup
+    # each, then tile offsets): batches just below, at and just above tile
+    # edges, and ones spanning many tiles, with short messages (one to three
+    # slices) and some empty ones.  The first-slice table is compared whole
+    # with the prefix sums of the slice counts.
     g = W.rng(W.SEED_BASE + 0x305 + n)
     lengths = (g.integers(0, 97, size=n) * 8).astype(np.int64)
     lengths[g.random(n) < 0.05] = 0
@@ -197,6 +199,11 @@ def test_scan_chunk_boundaries(torch_dev, n):
     _say("batch scan edges", n, int(lengths.sum()))
     offs, got, b = _run_batch(torch_dev, keys, lengths, dirs, data)
     assert b.skipped() == 0
+    slices = (lengths + 255) // 256
+    first = np.concatenate([[0], np.cumsum(slices)]).astype(np.int64)
+    table = b.ws.cpu().numpy()
+    assert table[0] == first[-1] and table[1] == 0
+    assert np.array_equal(table[2:2 + n + 1], first)
     if n < 64:
         check = range(n)
     else:
@@ -205,6 +212,40 @@ def test_scan_chunk_boundaries(torch_dev, n):
     for i in check:
         seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
         assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
+def test_scan_beyond_fused_tiles(torch_dev):
+    # More than 8192 tiles of 1024 descriptors: the tile offsets are then
+    # scanned by one workgroup and added by a third launch.  8,388,613
+    # one-block messages sharing two schedules; the whole first-slice table
+    # is compared with the prefix sums, and a sample of messages with the
+    # oracle.
+    torch = torch_dev
+    n = 8192 * 1024 + 5
+    g = W.rng(W.SEED_BASE + 0x30E)
+    keys = W.key_bundles(g, 2)
+    sch = T.key_schedules(keys)
+    d_sched = torch.empty(2 * T.DEVICE_SCHEDULE_BYTES, dtype=torch.uint8, device="cuda")
+    T.schedule_upload(sch, d_sched.data_ptr(), T._stream_handle(None))
+    offs = np.arange(n, dtype=np.int64) * 8
+    idx = np.arange(n) % 2
+    msgs = torch.from_numpy(T.msg_table(offs, offs, np.full(n, 8), idx, idx)).cuda()
+    data = W.uniform_bytes(g, 8 * n)
+    x = torch.from_numpy(data).cuda()
+    out = torch.zeros_like(x)
+    ws_bytes = T.batch_workspace_bytes(n)
+    ws = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device="cuda")
+    _say("batch scan beyond fused tiles", n)
+    T.batch_submit_ptr(msgs.data_ptr(), n, d_sched.data_ptr(), 2, x.data_ptr(), x.numel(),
+                       out.data_ptr(), out.numel(), ws.data_ptr(), ws_bytes)
+    torch.cuda.synchronize()
+    table = ws.cpu().numpy()
+    assert table[0] == n and table[1] == 0
+    assert np.array_equal(table[2:2 + n + 1], np.arange(n + 1))
+    got = out.cpu().numpy()
+    for i in W.rng(W.SEED_BASE + 0x30F).choice(n, 256, replace=False).tolist() + [0, n - 1]:
+        seg = slice(8 * i, 8 * i + 8)
+        assert np.array_equal(got[seg], oracle.tdes_ecb(keys[i % 2], data[seg], bool(i % 2))), i
 
 
 def test_offsets_beyond_4gib(torch_dev):
@@ -319,15 +360,15 @@ def test_every_configuration_gives_the_same_bytes(torch_dev):
     x = torch.from_numpy(data).cuda()
     keep = T.batch_get_config()
     try:
-        for kmax in (4, 8, 16):
-            for waves in (3, 4):
-                for mult in (1, 2, 3, 4):
-                    _say("batch config", kmax, waves, mult)
-                    T.batch_set_config(kmax, waves, mult)
-                    out = torch.full_like(x, 0xA5)
-                    b.submit(x, out)
-                    torch.cuda.synchronize()
-                    assert np.array_equal(out.cpu().numpy(), want), (kmax, waves, mult)
+        # the compiled variants (tdes_batch_config in include/tdes.h)
+        for kmax, waves in ((8, 4), (4, 4), (8, 3), (4, 3), (16, 3), (8, 5), (4, 5)):
+            for mult in (1, 2, 3, 4):
+                _say("batch config", kmax, waves, mult)
+                T.batch_set_config(kmax, waves, mult)
+                out = torch.full_like(x, 0xA5)
+                b.submit(x, out)
+                torch.cuda.synchronize()
+                assert np.array_equal(out.cpu().numpy(), want), (kmax, waves, mult)
     finally:
         T.batch_set_config(keep["kmax"], keep["waves"], keep["grid_mult"])
 
@@ -372,7 +413,7 @@ def test_batch_autotune_keeps_results(torch_dev):
     out = torch.full_like(x, 0xA5)
     _say("batch autotune")
     m = b.autotune(x, out, reps=2)
-    assert m["grid_mult"] in (1, 2, 3, 4) and m["kmax"] in (4, 8, 16) and m["waves"] in (3, 4)
+    assert m["grid_mult"] in (1, 2, 3, 4) and m["kmax"] in (4, 8, 16) and m["waves"] in (3, 4, 5)
     cur = T.batch_get_config()
     assert (cur["kmax"], cur["waves"], cur["grid_mult"]) == (m["kmax"], m["waves"], m["grid_mult"])
     torch.cuda.synchronize()

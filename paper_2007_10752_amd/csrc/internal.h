@@ -40,9 +40,10 @@ struct ReplicaKeyBits {
 };
 
 // Kernel argument for the table kernel: per round, the key chunks XORed into
-// the right half where the S-box windows sit (see spbox.hip).
+// the right half where the S-box windows sit (see spbox.hip): odd chunks,
+// even chunks, chunks 0 and 6 and chunk 7 for the half rotated left by 12.
 struct SpboxKeys {
-    uint32_t ke[48], ko[48], k0[48], k7[48];
+    uint32_t w[48][4];
 };
 
 // Device-resident key material of one schedule (tdes_schedule_upload,

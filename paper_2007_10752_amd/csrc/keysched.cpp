@@ -21,22 +21,25 @@ void device_schedule_words(const tdes_schedule &ks, uint32_t out[kDeviceSchedule
 
 // Key chunk s (bits 6s+1..6s+6 of the round key) lines up with S-box window
 // s of the right half R (bit i of R at position 32 - i):
-//   windows 1..6 sit at positions 27-4s .. 32-4s of R; odd and even windows
+//   windows 1..5 sit at positions 27-4s .. 32-4s of R; odd and even windows
 //   are disjoint, so one word carries the odd chunks and one the even ones;
-//   windows 0 and 7 wrap around, and are read from R rotated left by 7,
-//   at positions 2..7 and 6..11.
+//   windows 0 and 7 wrap around, and are read from R rotated left by 12,
+//   at positions 7..12 and 11..16; window 6 is read there too, at 15..20,
+//   apart from window 0, so one word carries chunks 0 and 6 and another
+//   chunk 7.
 void spbox_keys(const RoundSequence &seq, SpboxKeys *out) {
     for (int r = 0; r < 48; r++) {
+        const uint64_t k = seq.rk[r];
+        auto chunk = [k](int s) { return (uint32_t)((k >> (42 - 6 * s)) & 0x3Fu); };
         uint32_t ke = 0, ko = 0;
-        for (int s = 1; s <= 6; s++) {
-            const uint32_t ch = (uint32_t)((seq.rk[r] >> (42 - 6 * s)) & 0x3Fu);
-            if (s & 1) ko |= ch << (27 - 4 * s);
-            else ke |= ch << (27 - 4 * s);
+        for (int s = 1; s <= 5; s++) {
+            if (s & 1) ko |= chunk(s) << (27 - 4 * s);
+            else ke |= chunk(s) << (27 - 4 * s);
         }
-        out->ke[r] = ke;
-        out->ko[r] = ko;
-        out->k0[r] = (uint32_t)((seq.rk[r] >> 42) & 0x3Fu) << 2;
-        out->k7[r] = (uint32_t)(seq.rk[r] & 0x3Fu) << 6;
+        out->w[r][0] = ko;
+        out->w[r][1] = ke;
+        out->w[r][2] = (chunk(0) << 7) | (chunk(6) << 15);
+        out->w[r][3] = chunk(7) << 11;
     }
 }
 

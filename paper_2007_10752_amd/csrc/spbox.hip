@@ -5,15 +5,27 @@
 // S-box output already moved to its P position), indexed by the six R bits
 // the expansion feeds S-box s XORed with six round-key bits.  The tables
 // live in LDS, replicated 32 times and interleaved so that entry e of copy c
-// sits in bank c: lane l reads copy l % 32, so a lookup is free of bank
-// conflicts whatever the indices.  (8 tables x 64 entries x 32 copies x 4 B
-// = 64 KiB per workgroup.)
+// sits in bank c (byte 128 e + 4 c of the table): lane l reads copy l % 32,
+// so a lookup is free of bank conflicts whatever the indices.  (8 tables x
+// 64 entries x 32 copies x 4 B = 64 KiB per workgroup.)
 //
 // Key mixing: windows 1..6 of the expansion are contiguous in R (bit i of R
-// at position 32 - i); odd and even windows are disjoint, so XORing R once
-// with the odd key chunks and once with the even ones keys all six.
-// Windows 0 and 7 wrap around and are read from R rotated left by 7.  IP and
-// FP run once per block as rotate-and-mask code; the three DES passes are
+// at position 32 - i) and odd and even windows are disjoint, so XORing R
+// once with the odd key chunks and once with the even ones keys windows
+// 1..5.  Windows 0 and 7 wrap around; in R rotated left by 12 they sit at
+// positions 7..12 and 11..16, and window 6 at 15..20, so one XOR of the
+// rotated R keys windows 0 and 6 and another keys window 7.  Every window
+// then lies at or above position 7: a right shift brings it to bits 7..12,
+// and one three-input bitwise op masks it and adds the lane's copy offset,
+// which makes the LDS byte address (the table's base goes into the
+// instruction's offset field).  Shifts right, three-input bitwise ops and
+// XORs of vector registers are the VALU instructions that issue together
+// with another wave's; the mask and the copy offset are held in vector
+// registers, and so are the round keys (read from LDS, where the workgroup
+// copies them), so only the rotation issues alone.  The eight table words
+// and the left half are folded by four three-input XORs.
+//
+// IP and FP run once per block as delta swaps; the three DES passes are
 // fused as in the bitsliced kernel (FP then IP cancel between passes).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,33 +42,56 @@ namespace {
 constexpr int kThreads = 1024;
 constexpr int kCopies = 32;
 constexpr int kTableWords = 8 * 64 * kCopies;
+constexpr int kTableBytes = 64 * kCopies * 4;  // one S-box's table
+constexpr uint32_t kIndexMask = 63u << 7;      // entry index, scaled by 128 bytes
 
 __device__ __forceinline__ uint32_t rotl(uint32_t x, int s) {
     return __builtin_amdgcn_alignbit(x, x, 32 - s);
 }
 
-__device__ __forceinline__ uint32_t feistel(uint32_t R, const uint32_t *sp, uint32_t ke,
-                                            uint32_t ko, uint32_t k0, uint32_t k7) {
-    const uint32_t ro = R ^ ko, re = R ^ ke, rr = rotl(R, 7);
-    const uint32_t a0 = rr ^ k0, a7 = rr ^ k7;
-    // sp points at this lane's copy; entry v of table s is at sp[(s*64 + v) * 32]
-    const uint32_t v0 = sp[(0 * 64 + ((a0 >> 2) & 63u)) * kCopies];
-    const uint32_t v1 = sp[(1 * 64 + ((ro >> 23) & 63u)) * kCopies];
-    const uint32_t v2 = sp[(2 * 64 + ((re >> 19) & 63u)) * kCopies];
-    const uint32_t v3 = sp[(3 * 64 + ((ro >> 15) & 63u)) * kCopies];
-    const uint32_t v4 = sp[(4 * 64 + ((re >> 11) & 63u)) * kCopies];
-    const uint32_t v5 = sp[(5 * 64 + ((ro >> 7) & 63u)) * kCopies];
-    const uint32_t v6 = sp[(6 * 64 + ((re >> 3) & 63u)) * kCopies];
-    const uint32_t v7 = sp[(7 * 64 + ((a7 >> 6) & 63u)) * kCopies];
-    return v0 ^ v1 ^ v2 ^ v3 ^ v4 ^ v5 ^ v6 ^ v7;
+// A constant held in a vector register: the asm hides the value, so it is
+// not folded back into a scalar or literal operand.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t c) {
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(c));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// One round: L ^ f(R, K).  `sp` is the LDS table base; `lane` is this
+// lane's copy offset (4 (l % 32)); k = {odd chunks, even chunks, windows 0
+// and 6 of the rotated half, window 7 of the rotated half}.
+__device__ __forceinline__ uint32_t round_step(uint32_t L, uint32_t R, const uint8_t *sp,
+                                               uint32_t lane, uint32_t mask, uint4 k) {
+    const uint32_t ro = R ^ k.x, re = R ^ k.y, rr = rotl(R, 12);
+    const uint32_t a06 = rr ^ k.z, a7 = rr ^ k.w;
+    // (v >> sh) & mask | lane: 0xEA = (first & second) | third
+    auto look = [&](int s, uint32_t v, int sh) {
+        const uint32_t a = __builtin_amdgcn_bitop3_b32(v >> sh, mask, lane, 0xEA);
+        return *reinterpret_cast<const uint32_t *>(sp + s * kTableBytes + a);
+    };
+    const uint32_t v0 = look(0, a06, 0), v1 = look(1, ro, 16), v2 = look(2, re, 12);
+    const uint32_t v3 = look(3, ro, 8), v4 = look(4, re, 4), v5 = look(5, ro, 0);
+    const uint32_t v6 = look(6, a06, 8), v7 = look(7, a7, 4);
+    return xor3(xor3(v0, v1, v2), xor3(v3, v4, v5), xor3(v6, v7, L));
 }
 
 __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in, uint8_t *out,
                                                              size_t nblocks, SpboxKeys keys) {
     __shared__ uint32_t table[kTableWords];
+    __shared__ uint4 rk[48];
     for (int i = threadIdx.x; i < kTableWords; i += kThreads) table[i] = SP_TABLE[i / kCopies];
+    if (threadIdx.x < 48) {
+        const int r = threadIdx.x;
+        rk[r] = make_uint4(keys.w[r][0], keys.w[r][1], keys.w[r][2], keys.w[r][3]);
+    }
     __syncthreads();
-    const uint32_t *sp = table + (threadIdx.x % kCopies);
+    const uint8_t *sp = reinterpret_cast<const uint8_t *>(table);
+    const uint32_t lane = (threadIdx.x % kCopies) * 4u;
+    const uint32_t mask = in_vgpr(kIndexMask);
 
     const size_t stride = (size_t)gridDim.x * kThreads;
     for (size_t b = (size_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride) {
@@ -67,20 +102,20 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in,
         // Pass 1: L = X, R = Y.
 #pragma unroll 2
         for (int r = 0; r < 16; r += 2) {
-            X ^= feistel(Y, sp, keys.ke[r], keys.ko[r], keys.k0[r], keys.k7[r]);
-            Y ^= feistel(X, sp, keys.ke[r + 1], keys.ko[r + 1], keys.k0[r + 1], keys.k7[r + 1]);
+            X = round_step(X, Y, sp, lane, mask, rk[r]);
+            Y = round_step(Y, X, sp, lane, mask, rk[r + 1]);
         }
         // Pass 2 from R16 || L16: L = Y, R = X.
 #pragma unroll 2
         for (int r = 16; r < 32; r += 2) {
-            Y ^= feistel(X, sp, keys.ke[r], keys.ko[r], keys.k0[r], keys.k7[r]);
-            X ^= feistel(Y, sp, keys.ke[r + 1], keys.ko[r + 1], keys.k0[r + 1], keys.k7[r + 1]);
+            Y = round_step(Y, X, sp, lane, mask, rk[r]);
+            X = round_step(X, Y, sp, lane, mask, rk[r + 1]);
         }
         // Pass 3: L = X, R = Y.
 #pragma unroll 2
         for (int r = 32; r < 48; r += 2) {
-            X ^= feistel(Y, sp, keys.ke[r], keys.ko[r], keys.k0[r], keys.k7[r]);
-            Y ^= feistel(X, sp, keys.ke[r + 1], keys.ko[r + 1], keys.k0[r + 1], keys.k7[r + 1]);
+            X = round_step(X, Y, sp, lane, mask, rk[r]);
+            Y = round_step(Y, X, sp, lane, mask, rk[r + 1]);
         }
         uint32_t o0, o1;
         SP_FP(X, Y, o0, o1);  // preoutput R16 || L16 = Y || X

@@ -140,8 +140,10 @@ def bitslice_ecb(key_bytes, data):
 # ------------------------------------------------------------ table kernel --
 
 def spbox_keys_from_bytes(key_bytes):
-    w = np.frombuffer(key_bytes, dtype="<u4").reshape(4, 48)
-    return [list(map(int, w[i])) for i in range(4)]
+    """Per round: odd chunks, even chunks, chunks 0 and 6 and chunk 7 of the
+    half rotated left by 12."""
+    w = np.frombuffer(key_bytes, dtype="<u4").reshape(48, 4)
+    return [list(map(int, w[:, i])) for i in range(4)]
 
 
 def _rotl(x, s):
@@ -185,13 +187,13 @@ def spbox_ecb(key_bytes, data):
     """Emulate tdes_spbox_kernel block by block, given its key argument."""
     text = _header("spbox_gen.h")
     sp = _int_array(text, "SP_TABLE")
-    ke, ko, k0, k7 = spbox_keys_from_bytes(key_bytes)
+    ko, ke, k06, k7 = spbox_keys_from_bytes(key_bytes)
 
     def f(R, r):
-        ro, re_, rr = R ^ ko[r], R ^ ke[r], _rotl(R, 7)
-        a0, a7 = rr ^ k0[r], rr ^ k7[r]
-        idx = [(a0 >> 2) & 63, (ro >> 23) & 63, (re_ >> 19) & 63, (ro >> 15) & 63,
-               (re_ >> 11) & 63, (ro >> 7) & 63, (re_ >> 3) & 63, (a7 >> 6) & 63]
+        ro, re_, rr = R ^ ko[r], R ^ ke[r], _rotl(R, 12)
+        a06, a7 = rr ^ k06[r], rr ^ k7[r]
+        idx = [(a06 >> 7) & 63, (ro >> 23) & 63, (re_ >> 19) & 63, (ro >> 15) & 63,
+               (re_ >> 11) & 63, (ro >> 7) & 63, (a06 >> 15) & 63, (a7 >> 11) & 63]
         v = 0
         for s in range(8):
             v ^= sp[64 * s + idx[s]]

@@ -1,4 +1,5 @@
-// Table-driven 3DES-EDE ECB kernel for gfx950: one 64-bit block per lane.
+// Table-driven 3DES-EDE ECB kernel for gfx950: one 64-bit block per lane
+// (up to four at a time, interleaved, in its grid-stride loop).
 //
 // Each round (Sec. III-B) computes f(R, K) as the XOR of eight lookups in
 // combined S-box + straight-permutation tables SP_s[64] (32-bit words: the
@@ -79,6 +80,51 @@ __device__ __forceinline__ uint32_t round_step(uint32_t L, uint32_t R, const uin
     return xor3(xor3(v0, v1, v2), xor3(v3, v4, v5), xor3(v6, v7, L));
 }
 
+// The 48 rounds and FP/IP of N blocks at once (in + 8 b, stride blocks
+// apart), interleaved so that one block's LDS reads wait while the others
+// compute.
+template <int N>
+__device__ __forceinline__ void blocks(const uint8_t *in, uint8_t *out, size_t b, size_t stride,
+                                       const uint8_t *sp, uint32_t lane, uint32_t mask,
+                                       const uint4 *rk) {
+    uint32_t X[N], Y[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(in + 8 * (b + i * stride));
+        SP_IP(w.x, w.y, X[i], Y[i]);
+    }
+    // Pass 1: L = X, R = Y.
+#pragma unroll 2
+    for (int r = 0; r < 16; r += 2) {
+#pragma unroll
+        for (int i = 0; i < N; i++) X[i] = round_step(X[i], Y[i], sp, lane, mask, rk[r]);
+#pragma unroll
+        for (int i = 0; i < N; i++) Y[i] = round_step(Y[i], X[i], sp, lane, mask, rk[r + 1]);
+    }
+    // Pass 2 from R16 || L16: L = Y, R = X.
+#pragma unroll 2
+    for (int r = 16; r < 32; r += 2) {
+#pragma unroll
+        for (int i = 0; i < N; i++) Y[i] = round_step(Y[i], X[i], sp, lane, mask, rk[r]);
+#pragma unroll
+        for (int i = 0; i < N; i++) X[i] = round_step(X[i], Y[i], sp, lane, mask, rk[r + 1]);
+    }
+    // Pass 3: L = X, R = Y.
+#pragma unroll 2
+    for (int r = 32; r < 48; r += 2) {
+#pragma unroll
+        for (int i = 0; i < N; i++) X[i] = round_step(X[i], Y[i], sp, lane, mask, rk[r]);
+#pragma unroll
+        for (int i = 0; i < N; i++) Y[i] = round_step(Y[i], X[i], sp, lane, mask, rk[r + 1]);
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        uint32_t o0, o1;
+        SP_FP(X[i], Y[i], o0, o1);  // preoutput R16 || L16 = Y || X
+        *reinterpret_cast<uint2 *>(out + 8 * (b + i * stride)) = make_uint2(o0, o1);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in, uint8_t *out,
                                                              size_t nblocks, SpboxKeys keys) {
     __shared__ uint32_t table[kTableWords];
@@ -93,34 +139,13 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in,
     const uint32_t lane = (threadIdx.x % kCopies) * 4u;
     const uint32_t mask = in_vgpr(kIndexMask);
 
+    // Grid-stride over blocks: four at a time while this thread has four,
+    // then two, then one.
     const size_t stride = (size_t)gridDim.x * kThreads;
-    for (size_t b = (size_t)blockIdx.x * kThreads + threadIdx.x; b < nblocks; b += stride) {
-        const uint2 w = *reinterpret_cast<const uint2 *>(in + 8 * b);
-        uint32_t L, R;
-        SP_IP(w.x, w.y, L, R);
-        uint32_t X = L, Y = R;
-        // Pass 1: L = X, R = Y.
-#pragma unroll 2
-        for (int r = 0; r < 16; r += 2) {
-            X = round_step(X, Y, sp, lane, mask, rk[r]);
-            Y = round_step(Y, X, sp, lane, mask, rk[r + 1]);
-        }
-        // Pass 2 from R16 || L16: L = Y, R = X.
-#pragma unroll 2
-        for (int r = 16; r < 32; r += 2) {
-            Y = round_step(Y, X, sp, lane, mask, rk[r]);
-            X = round_step(X, Y, sp, lane, mask, rk[r + 1]);
-        }
-        // Pass 3: L = X, R = Y.
-#pragma unroll 2
-        for (int r = 32; r < 48; r += 2) {
-            X = round_step(X, Y, sp, lane, mask, rk[r]);
-            Y = round_step(Y, X, sp, lane, mask, rk[r + 1]);
-        }
-        uint32_t o0, o1;
-        SP_FP(X, Y, o0, o1);  // preoutput R16 || L16 = Y || X
-        *reinterpret_cast<uint2 *>(out + 8 * b) = make_uint2(o0, o1);
-    }
+    size_t b = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    for (; b + 3 * stride < nblocks; b += 4 * stride) blocks<4>(in, out, b, stride, sp, lane, mask, rk);
+    for (; b + stride < nblocks; b += 2 * stride) blocks<2>(in, out, b, stride, sp, lane, mask, rk);
+    if (b < nblocks) blocks<1>(in, out, b, stride, sp, lane, mask, rk);
 }
 
 // Workgroups that fit on the current device at once, cached per device
@@ -150,7 +175,9 @@ hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, siz
                         hipStream_t stream) {
     const size_t nblocks = nbytes / 8;
     size_t grid = (nblocks + kThreads - 1) / kThreads;
-    const size_t cap = (size_t)resident_workgroups();
+    // Two workgroups per resident slot: the second wave of workgroups fills
+    // the slots of those that finish early.
+    const size_t cap = 2 * (size_t)resident_workgroups();
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL(tdes_spbox_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, in,
                        out, nblocks, k);

@@ -143,6 +143,35 @@ def test_64mib_full(torch_dev, kernel, two_key):
     assert np.array_equal(rows, oracle.tdes_ecb(key, sample, decrypt=True))
 
 
+# Sizes past the point where a lane takes several blocks of the grid-stride
+# loop (the table kernel at most 1,024 workgroups of 1,024 lanes: 2^20 blocks
+# per sweep), with remainders that leave lanes four, three, two or one block
+# more: checked on the blocks near every multiple of 2^20 and a seeded sample.
+STRIDE_CASES = [(3 << 20) + 517, (5 << 20) + 9, (7 << 20) + 3]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("nblk", STRIDE_CASES)
+def test_grid_stride_remainders(torch_dev, kernel, nblk):
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x58)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 8 * nblk)
+    _say("grid-stride", kernel, nblk)
+    x = torch.from_numpy(data).cuda()
+    out = torch.empty_like(x)
+    T.encrypt(key, x, out, kernel=kernel)
+    torch.cuda.synchronize()
+    near = [np.arange(max(0, k - 1024), min(nblk, k + 1024)) for k in range(0, nblk + 1, 1 << 20)]
+    idx = np.concatenate(near + [np.arange(nblk - 2048, nblk),
+                                 W.rng(W.SEED_BASE + 0x59).choice(nblk, 1 << 14, replace=False)])
+    idx = np.unique(idx)
+    ti = torch.from_numpy(idx).cuda()
+    got = out.view(-1, 8)[ti].cpu().numpy().reshape(-1)
+    sample = data.reshape(-1, 8)[idx].reshape(-1)
+    assert np.array_equal(got, oracle.tdes_ecb(key, sample))
+
+
 GIB = 1 << 30
 
 

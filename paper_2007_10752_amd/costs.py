@@ -12,7 +12,9 @@ bitsliced (per 32 blocks = one lane):
     selects per pair)
   IP, E, P and FP are register renaming: no operations.
 table (SP-box) kernel (per block):
-  48 rounds x (1 rotate + 4 key XORs + 8 index extracts + 8 XORs)
+  48 rounds x (1 rotate + 4 key XORs + 6 shifts and 8 mask-and-offset ops
+  that turn the 8 windows into LDS addresses + 4 three-input XORs folding
+  the 8 table words into the other half)
   + IP and FP as delta swaps (the operation counts the generator writes
   beside them); plus 8 LDS reads a round.
 HBM traffic: every block is read once and written once: 16 bytes.
@@ -26,8 +28,9 @@ GEN = os.path.join(HERE, "csrc", "generated")
 # MI355X: 256 CUs x 4 SIMDs x 32 lanes/clock x 2.4 GHz, 32-bit VALU lane-ops/s.
 # Wave64 bitwise VALU instructions issue at 32 lanes per clock per SIMD (two
 # waves' instructions per 4-clock window); the probe kernels in
-# include/tdes_probe.h sustain ~77 T (v_xor_b32), above the 39.3 T that 16
-# lanes per clock would allow.
+# include/tdes_probe.h sustain 55-60 T under load (v_xor_b32, v_bitop3_b32,
+# at a lower shader clock), above the 39.3 T that 16 lanes per clock would
+# allow at 2.4 GHz.
 VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
 HBM_BYTES_PER_BLOCK = 16
@@ -57,7 +60,7 @@ def bitslice_ops_per_block():
 def spbox_ops_per_block():
     text = _read("spbox_gen.h")
     ipfp = sum(int(g) for g in re.findall(r"\((\d+) operations\)", text))
-    return 48 * (1 + 4 + 8 + 8) + ipfp
+    return 48 * (1 + 4 + 6 + 8 + 4) + ipfp
 
 
 def ops_per_block(kernel):

@@ -17,8 +17,9 @@ digest the oracle wrote (tests/golden), and block by block on the sample.
 Beside the headline, the other workloads are reported in their own
 objects: 32 KiB encrypt and decrypt (launch-bound), 64 MiB with 3-key and
 2-key bundles in both directions on both kernels, 1 GiB of all-zero and
-repeating-pattern input, the batched form (16,384 messages, also from raw
-key bundles), the host-resident form and the request server.
+repeating-pattern input, the batched form (16,384 messages: a stream of
+batches over two streams, one stream, one submit alone, and from raw key
+bundles), the host-resident form and the request server.
 
 Prints one JSON line.
 """
@@ -325,11 +326,52 @@ def batched_section(steps, settle_s=0.3):
             b.submit(x, out)
         torch.cuda.synchronize()
     tuned = b.autotune(x, out, reps=3)
-    t_batch = time_launches(lambda: b.submit(x, out), max(3, steps), stream)
+    t_single = time_launches(lambda: b.submit(x, out), max(3, steps), stream)
     sched = tdes.key_schedule(lay["keys"][0])
     sh = int(stream.cuda_stream)
     t_plain = time_launches(lambda: tdes.ecb_crypt_ptr(sched, 0, 1, x.data_ptr(), out.data_ptr(),
                                                        total, sh), max(3, steps), stream)
+    # A stream of batches, as a server runs them: back-to-back submits,
+    # alternating between two streams, each batch with its own workspace and
+    # output, so that the last waves of one batch share the GPU with the
+    # first of the next.  Also on one stream, and the plain kernel on the
+    # same bytes the same two ways.  (Two streams created one after the
+    # other: HIP gives them different hardware queues, which the null stream
+    # and a later stream need not have.)
+    b2 = tdes.Batch(lay["keys"], lay["offsets"], lay["offsets"], lay["lengths"], lay["dirs"])
+    out2 = torch.empty_like(x)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def batch_on(bb, o, st):
+        return lambda: bb.submit(x, o, stream=st)
+
+    def plain_on(o, st):
+        return lambda: tdes.ecb_crypt_ptr(sched, 0, 1, x.data_ptr(), o.data_ptr(), total,
+                                          int(st.cuda_stream))
+
+    def stream_of(fns, k):
+        def one():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(k):
+                fns[i % len(fns)]()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / k
+        # the batch set-up above leaves the GPU idle long enough for the
+        # clock to fall back: settle on this loop first
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < settle_s:
+            one()
+        return sorted(one() for _ in range(3))[1]
+
+    k_stream = max(20, steps)
+    lanes = [batch_on(b, out, s1), batch_on(b2, out2, s2)]
+    t_batch = stream_of(lanes, k_stream)
+    t_one_stream = stream_of(lanes[:1], k_stream)
+    t_plain2 = stream_of([plain_on(out, s1), plain_on(out2, s2)], k_stream)
+    b.submit(x, out)
+    b2.submit(x, out2, stream=stream)
+    streams_equal = bool(torch.equal(out, out2))
     scheds = tdes.key_schedules(lay["keys"])
     offs, lens, dirs = lay["offsets"].tolist(), lay["lengths"].tolist(), lay["dirs"].tolist()
     xb, ob = x.data_ptr(), out.data_ptr()
@@ -352,10 +394,17 @@ def batched_section(steps, settle_s=0.3):
     raw = raw_keys_variant(b, lay, x, out, steps, settle_s)
     return {"value": round(total / t_batch / 1e9, 3), "unit": "GB/s",
             "ms": round(t_batch * 1e3, 4), "messages": len(lens), "bytes": total,
+            "value_is": "%d back-to-back batches alternating over two streams, wall time per "
+                        "batch (median of 3 runs)" % k_stream,
+            "one_stream_GBps": round(total / t_one_stream / 1e9, 3),
+            "single_submit_GBps": round(total / t_single / 1e9, 3),
+            "single_submit_ms": round(t_single * 1e3, 4),
+            "two_streams_outputs_equal": streams_equal,
             "graph_replay_GBps": round(total / t_graph / 1e9, 3),
             "autotuned": {"kmax": tuned["kmax"], "waves_per_simd": tuned["waves"],
                           "grid_multiplier": tuned["grid_mult"], "saved": tuned["saved"]},
             "plain_same_bytes_GBps": round(total / t_plain / 1e9, 3),
+            "plain_same_bytes_two_streams_GBps": round(total / t_plain2 / 1e9, 3),
             "per_message_launches_GBps": round(total / t_loop / 1e9, 3),
             "from_raw_keys": raw,
             "config": "16384 msgs, lognormal median 4 KiB sigma 1, clip 8 B..1 MiB, "

@@ -5,7 +5,8 @@ v_bitop3_b32 / v_xor_b32 / v_perm_b32 ... on one lane):
 
 bitsliced (per 32 blocks = one lane):
   48 rounds x (S-box gates + 32 three-input XORs of the outputs into the other
-  half, which also carry the key masks, + 16 key XORs of second-use inputs)
+  half, which also carry the key masks, + key XORs of the second-use inputs
+  whose masks are not folded into their gates: BS_XORS_PER_ROUND in all)
   + 4 transposes of 32 words (2 in, 2 out), each 16 pairs x
     (2 + 2 + 4 + 4 + 4) ops (byte stages: one v_perm_b32 per word; bit
     stages: two shifts, or a shift and an addition, and two v_bitop3_b32

@@ -12,7 +12,15 @@
 namespace tdes {
 
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v3u __attribute__((ext_vector_type(3)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+constexpr bool box_ndup_fits() {
+    for (int j = 0; j < 8; j++)
+        if (BS_BOX_NDUP[j] < 0 || BS_BOX_NDUP[j] > 4) return false;
+    return true;
+}
+static_assert(box_ndup_fits(), "an S-box has at most 4 second-use inputs");
 
 #ifndef TDES_BS_PIPE
 #define TDES_BS_PIPE 2  // S-boxes between a mask request and its use
@@ -23,23 +31,30 @@ typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 // instruction with a scalar operand is never issued together with another
 // wave's).
 struct LdsBoxLoad {
-    // n (0, 2 or 4) is a compile-time constant after inlining; only words that
-    // are used are read, so no read's destination register is reused while
-    // the read is in flight
+    // n (0..4, the box's second uses) is a compile-time constant after
+    // inlining; only words that are used are read, so no read's destination
+    // register is reused while the read is in flight
     template <class P>
     __device__ __forceinline__ void operator()(BsBoxMasks &m, P p, int n) const {
         // volatile keeps each read where it is issued (otherwise the reads
         // that cross the loop back edge are folded into reads at first use)
         typedef const volatile __attribute__((address_space(3))) v4u lds_v4u;
+        typedef const volatile __attribute__((address_space(3))) v3u lds_v3u;
         typedef const volatile __attribute__((address_space(3))) v2u lds_v2u;
+        typedef const volatile __attribute__((address_space(3))) uint32_t lds_u;
         const v4u a = *(lds_v4u *)p;
         m.o[0] = a[0]; m.o[1] = a[1]; m.o[2] = a[2]; m.o[3] = a[3];
         if (n == 4) {
             const v4u b = *(lds_v4u *)(p + 4);
             m.e[0] = b[0]; m.e[1] = b[1]; m.e[2] = b[2]; m.e[3] = b[3];
+        } else if (n == 3) {
+            const v3u b = *(lds_v3u *)(p + 4);
+            m.e[0] = b[0]; m.e[1] = b[1]; m.e[2] = b[2];
         } else if (n == 2) {
             const v2u b = *(lds_v2u *)(p + 4);
             m.e[0] = b[0]; m.e[1] = b[1];
+        } else if (n == 1) {
+            m.e[0] = *(lds_u *)(p + 4);
         }
     }
 };

@@ -19,6 +19,15 @@
 // wins.  The result is checked exhaustively here and again by the Python
 // emitter.
 //
+// Restricted inputs (SBOX_RESTRICT, a bit mask of inputs 0..5): such an
+// input may enter only gates whose other live operand is one signal, so that
+// the kernel can pass the key mask the input needs in the free third slot
+// (the gate then computes its function of input ^ mask) instead of XORing
+// it in first.  Restricted inputs are never reused as signals, selectors or
+// operands of three-signal gates; where no other signal splits a care set,
+// the search adds a copy gate of a restricted input (the same cost as the
+// XOR it would save).
+//
 // Usage: sbox_synth <restarts> <seed> <box table: 64 values, row-major 4x16>
 // Prints the best network as text.
 #include <cstdint>
@@ -52,6 +61,11 @@ struct Net {
 };
 
 static std::mt19937_64 rng;
+static int g_restrict = 0;
+static inline bool restricted(int s) { return s < 6 && ((g_restrict >> s) & 1); }
+
+// Thrown when a restart recurses too deep; the restart is dropped.
+struct TooDeep {};
 
 static u64 input_tt(int q) {
     u64 t = 0;
@@ -62,6 +76,7 @@ static u64 input_tt(int q) {
 
 static bool find_existing(const Net &n, u64 t, u64 care, Ref *r) {
     for (int s = (int)n.tt.size() - 1; s >= 0; s--) {
+        if (restricted(s)) continue;
         u64 d = (n.tt[s] ^ t) & care;
         if (d == 0) { *r = {s, 0}; return true; }
         if (d == care) { *r = {s, 1}; return true; }
@@ -74,13 +89,45 @@ static bool find_existing(const Net &n, u64 t, u64 care, Ref *r) {
 static bool find_single(const Net &n, u64 t, u64 care, Gate *out, bool pick_random) {
     int ns = (int)n.tt.size();
     long found = 0;
+    // two-operand gates of a restricted input and one other signal, written
+    // LUT3(i, j, j): the kernel puts the mask in the third slot
+    for (int i = 0; i < 6; i++) {
+        if (!restricted(i)) continue;
+        u64 A = n.tt[i];
+        for (int j = 0; j < ns; j++) {
+            if (j == i || restricted(j)) continue;
+            u64 B = n.tt[j];
+            int imm = 0, dc = 0;  // 4-entry table, index (a << 1) | b
+            bool ok = true;
+            for (int p = 0; p < 4 && ok; p++) {
+                u64 m = ((p & 2) ? A : ~A) & ((p & 1) ? B : ~B) & care;
+                if (!m) { dc |= 1 << p; continue; }
+                u64 on = m & t;
+                if (on == m) imm |= 1 << p;
+                else if (on != 0) ok = false;
+            }
+            if (!ok) continue;
+            found++;
+            if (!pick_random || (rng() % found) == 0) {
+                imm |= (int)(rng() & 0xf) & dc;
+                int imm8 = 0;
+                for (int idx = 0; idx < 8; idx++)
+                    imm8 |= ((imm >> (idx >> 1)) & 1) << idx;
+                *out = {i, j, j, imm8};
+                if (!pick_random) return true;
+            }
+        }
+    }
     for (int i = 0; i < ns; i++) {
+        if (restricted(i)) continue;
         u64 A = n.tt[i];
         for (int j = i + 1; j < ns; j++) {
+            if (restricted(j)) continue;
             u64 B = n.tt[j];
             u64 ab[4] = {~A & ~B & care, ~A & B & care, A & ~B & care, A & B & care};
             // quick reject on the pair alone is not possible in general; go on
             for (int k = j + 1; k < ns; k++) {
+                if (restricted(k)) continue;
                 u64 C = n.tt[k];
                 int imm = 0, dc = 0;
                 bool ok = true;
@@ -132,18 +179,31 @@ static Ref solve(Net &n, u64 t, u64 care, int depth) {
     if (find_existing(n, t, care, &r)) return r;
     Gate g1;
     if (find_single(n, t, care, &g1, true)) return {add_gate(n, g1), 0};
-    if (depth > 64) { fprintf(stderr, "depth limit\n"); exit(2); }
+    if (depth > 64) throw TooDeep();
 
     // choose a selector signal
     int ns = (int)n.tt.size();
     int best_sc = 1 << 30;
     std::vector<int> best;
     for (int s = 0; s < ns; s++) {
+        if (restricted(s)) continue;
         u64 c1 = care & n.tt[s], c0 = care & ~n.tt[s];
         if (!c0 || !c1) continue;
         int sc = cost_est(n, t, c0) + cost_est(n, t, c1);
         if (sc < best_sc) { best_sc = sc; best.clear(); }
         if (sc == best_sc) best.push_back(s);
+    }
+    if (best.empty()) {
+        // only restricted inputs split the care set: copy one (LUT3(i, j, j)
+        // = input i) and split on the copy
+        std::vector<int> cand;
+        for (int i = 0; i < 6; i++)
+            if (restricted(i) && (care & n.tt[i]) && (care & ~n.tt[i])) cand.push_back(i);
+        if (cand.empty()) throw TooDeep();  // cannot happen for a function of the inputs
+        int i = cand[rng() % cand.size()], j = (i + 1) % 6;
+        while (restricted(j)) j = (j + 1) % 6;
+        add_gate(n, {i, j, j, 0xF0});
+        return solve(n, t, care, depth + 1);
     }
     int sel = best[rng() % best.size()];
     int first_side = (int)(rng() & 1);
@@ -205,7 +265,7 @@ static Ref split_join(Net &n, u64 t, u64 care, int sel, int first_side, int dept
     }
     Ref href = solve(n, best_th, best_ch, depth + 1);
     // build the join gate LUT3(sel, g, h)
-    int gi = gref.idx < 0 ? 0 : gref.idx, hi = href.idx < 0 ? 0 : href.idx;
+    int gi = gref.idx < 0 ? sel : gref.idx, hi = href.idx < 0 ? sel : href.idx;
     int imm = 0;
     for (int idx = 0; idx < 8; idx++) {
         int sv = (idx >> 2) & 1, gv = ((idx >> 1) & 1) ^ gref.neg, hv = (idx & 1) ^ href.neg;
@@ -242,10 +302,11 @@ static Net prune(const Net &n) {
 
 int main(int argc, char **argv) {
     if (argc != 4 + 63) {
-        fprintf(stderr, "usage: %s restarts seed v0 .. v63   (env SBOX_LOOKAHEAD=depth)\n", argv[0]);
+        fprintf(stderr, "usage: %s restarts seed v0 .. v63   (env SBOX_LOOKAHEAD=depth, SBOX_RESTRICT=mask)\n", argv[0]);
         return 1;
     }
     if (getenv("SBOX_LOOKAHEAD")) g_lookahead = atoi(getenv("SBOX_LOOKAHEAD"));
+    if (getenv("SBOX_RESTRICT")) g_restrict = atoi(getenv("SBOX_RESTRICT")) & 63;
     int restarts = atoi(argv[1]);
     rng.seed(strtoull(argv[2], 0, 0));
     int box[64];
@@ -264,9 +325,13 @@ int main(int argc, char **argv) {
         for (int q = 0; q < 6; q++) n.tt.push_back(input_tt(q));
         int order[4] = {0, 1, 2, 3};
         for (int i = 3; i > 0; i--) std::swap(order[i], order[rng() % (i + 1)]);
-        for (int oi = 0; oi < 4; oi++) {
-            int q = order[oi];
-            n.out[q] = solve(n, target[q], ~0ull, 0);
+        try {
+            for (int oi = 0; oi < 4; oi++) {
+                int q = order[oi];
+                n.out[q] = solve(n, target[q], ~0ull, 0);
+            }
+        } catch (const TooDeep &) {
+            continue;
         }
         Net p = prune(n);
         for (int q = 0; q < 4; q++) {

@@ -69,6 +69,47 @@ def _int_const(text, name):
     return int(re.search(r"%s = (\d+)" % name, text).group(1))
 
 
+_OPERAND = re.compile(r"^(?:r\[(\d+)\]|d\[(\d+)\]|m\.o\[(\d+)\]|m\.e\[(\d+)\]|(\w+))$")
+
+
+def _operand(text):
+    m = _OPERAND.match(text.strip())
+    assert m, text
+    for kind, g in zip(("r", "d", "o", "e"), m.groups()[:4]):
+        if g is not None:
+            return (kind, int(g))
+    return ("v", m.group(5))
+
+
+def _piped_round_boxes(text):
+    """The statements of the generated bs_round_piped, per S-box: (box,
+    [(kind, lhs, operands, imm)]) with kind "lut" (v_bitop3_b32) or "xor";
+    the mask loads and scheduling barriers are left out."""
+    body = text[text.index("void bs_round_piped("):]
+    body = body[:body.index("\n}\n")]
+    boxes = []
+    for line in body.splitlines():
+        line = line.strip()
+        mb = re.match(r"const BsBoxMasks &m = pm\[(\d+)\];", line)
+        if mb:
+            boxes.append((int(mb.group(1)), []))
+            continue
+        ma = re.match(r"(?:const uint32_t )?(\w+|d\[\d+\]) = (.*);(?:\s*//.*)?$", line)
+        if not ma or not boxes:
+            continue
+        lhs, rhs = _operand(ma.group(1)), ma.group(2)
+        lhs = ("d", lhs[1]) if lhs[0] == "d" else ("v", lhs[1])
+        ml = re.match(r"__builtin_amdgcn_bitop3_b32\((.*), (0x[0-9a-f]+)\)$", rhs)
+        if ml:
+            ops = [_operand(o) for o in ml.group(1).split(",")]
+            boxes[-1][1].append(("lut", lhs, ops, int(ml.group(2), 16)))
+        else:
+            ops = [_operand(o) for o in rhs.split("^")]
+            boxes[-1][1].append(("xor", lhs, ops, 0))
+    assert [b for b, _ in boxes] == list(range(8)), [b for b, _ in boxes]
+    return boxes
+
+
 def bitslice_ecb(key_bytes, data):
     """Emulate tdes_bitslice_kernel on up to 32 blocks (one lane), given the
     kernel's key argument (tdes_kernel_key_bytes)."""
@@ -76,15 +117,11 @@ def bitslice_ecb(key_bytes, data):
     ktext = _header("bitslice_keys_gen.h")
     ip_l, ip_r = _int_array(text, "BS_IP_L"), _int_array(text, "BS_IP_R")
     fp_src = _int_array(text, "BS_FP_SRC")
-    e_src = _int_array(ktext, "kBsESrc")
-    dup_e = _int_array(ktext, "kBsDupE")
-    out_word = _int_array(ktext, "kBsOutWord")
     c = {k: _int_const(ktext, k) for k in ("kBsBoxMasks", "kBsRoundMasks", "kBsInitY",
                                            "kBsRemask16", "kBsRemask32", "kBsFinalX",
                                            "kBsNumMasks")}
     box_dup = _int_array(ktext, "kBsBoxDup")
     km = _bs_masks(key_bytes, box_dup, c)
-    nets = load_networks()
 
     d = np.asarray(data, dtype=np.uint8)
     nblk = d.size // 8
@@ -97,24 +134,34 @@ def bitslice_ecb(key_bytes, data):
     X = [plane[i] for i in ip_l]
     Y = [plane[i] ^ km[c["kBsInitY"] + n] for n, i in enumerate(ip_r)]
 
-    dup_set = set(dup_e)
+    boxes = _piped_round_boxes(text)
 
     def rnd(dst, src, t):
-        for box in range(8):
+        # the emitted bs_round_piped, statement by statement: box j reads its
+        # masks o[q] (slot q) and e[i] (slot 4 + i) of round t
+        for box, stmts in boxes:
             m = km[c["kBsRoundMasks"] * t + c["kBsBoxMasks"] * box:]
-            sig, i = [], 0
-            for q in range(6):
-                e = 6 * box + q
-                v = src[e_src[e]]
-                if e in dup_set:        # i-th second-use input of this box
-                    v ^= m[4 + i]
-                    i += 1
-                sig.append(v)
-            for a, b, cc, imm in nets[box]["gates"]:
-                sig.append(_lut3(imm, sig[a], sig[b], sig[cc]))
-            for q, (sg, neg) in enumerate(nets[box]["outs"]):
-                j = out_word[4 * box + q]
-                dst[j] ^= sig[sg] ^ (M32 if neg else 0) ^ m[q]
+            env = {}
+
+            def val(tok):
+                kind, a = tok
+                if kind == "r":
+                    return src[a]
+                if kind == "d":
+                    return dst[a]
+                if kind == "o":
+                    return m[a]
+                if kind == "e":
+                    return m[4 + a]
+                return env[a]
+
+            for kind, lhs, ops, imm in stmts:
+                v = [val(o) for o in ops]
+                res = _lut3(imm, *v) if kind == "lut" else (v[0] ^ v[1] if len(v) == 2 else v[0])
+                if lhs[0] == "d":
+                    dst[lhs[1]] = res
+                else:
+                    env[lhs[1]] = res
 
     for t in range(0, 16, 2):
         rnd(X, Y, t)

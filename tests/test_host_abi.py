@@ -20,7 +20,8 @@ import oracle
 from paper_2007_10752_amd import tdes as T
 from paper_2007_10752_amd import workloads as W
 from paper_2007_10752_amd.gen import des_tables as DT
-from paper_2007_10752_amd.gen.networks import evaluate, load_networks
+from paper_2007_10752_amd.gen import emit
+from paper_2007_10752_amd.gen.networks import MASK_BASE, evaluate, load_networks
 
 import emulate_kernels as E
 
@@ -255,6 +256,33 @@ def test_sbox_networks_exhaustive():
     for box in range(8):
         for v in range(64):
             assert evaluate(nets[box], v) == oracle.sbox(box, v), (box, v)
+
+
+def test_folded_networks_exhaustive():
+    # The networks as the kernels run them: a second-use input whose key mask
+    # is folded into its gates enters them raw, with the mask as the third
+    # operand; every output must be the S-box of (input ^ mask), for all 64
+    # inputs and every value of the folded masks.
+    nets = load_networks()
+    _, folded = emit.plan(nets)
+    assert len(folded) == 48 - int(re.search(r"#define BS_XORS_PER_ROUND (\d+)",
+                                             E._header("bitslice_gen.h")).group(1))
+    for box in range(8):
+        f = emit.box_network(nets, box)
+        for v in range(64):
+            for mbits in range(1 << len(f["folded"])):
+                sig = {q: (v >> (5 - q)) & 1 for q in range(6)}
+                eff = v
+                for i, q in enumerate(f["folded"]):
+                    m = (mbits >> i) & 1
+                    sig[MASK_BASE + q] = m
+                    eff ^= m << (5 - q)
+                for i, (a, b, c, imm) in enumerate(f["gates"]):
+                    sig[6 + i] = (imm >> ((sig[a] << 2) | (sig[b] << 1) | sig[c])) & 1
+                got = 0
+                for sg, neg in f["outs"]:
+                    got = (got << 1) | (sig[sg] ^ neg)
+                assert got == oracle.sbox(box, eff), (box, v, mbits)
 
 
 def test_generated_headers_are_current():

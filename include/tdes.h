@@ -54,7 +54,11 @@ typedef enum { TDES_ENCRYPT = 0, TDES_DECRYPT = 1 } tdes_dir;
 
 /* Kernel selection for tdes_ecb_crypt. */
 typedef enum {
-    TDES_KERNEL_AUTO = 0,     /* the library's choice (bitsliced)          */
+    TDES_KERNEL_AUTO = 0,     /* the library's choice: the table kernel up
+                                 to the bytes one wave of its resident
+                                 workgroups covers at one block per lane
+                                 (4 MiB on 256 CUs; lower latency), the
+                                 bitsliced kernel above (higher throughput) */
     TDES_KERNEL_BITSLICE = 1, /* 32 blocks per lane as bit planes; S-boxes
                                  as gate networks, E/P/IP/FP as renaming   */
     TDES_KERNEL_SPBOX = 2     /* one block per lane; S-box+P tables in LDS */

@@ -78,6 +78,20 @@ tdes_status tdes::set_last_error(tdes_status st, const char *msg) {
     return st;
 }
 
+hipError_t tdes::launch_ecb_auto(const tdes_schedule &ks, int dir, const uint8_t *in,
+                                 uint8_t *out, size_t nbytes, hipStream_t stream) {
+    if (nbytes <= spbox_one_pass_bytes()) {
+        RoundSequence seq;
+        round_sequence(ks, dir, &seq);
+        SpboxKeys k;
+        spbox_keys(seq, &k);
+        return launch_spbox(k, in, out, nbytes, stream);
+    }
+    BitsliceKeys k;
+    bitslice_keys(ks, dir, &k);
+    return launch_bitslice(k, in, out, nbytes, stream);
+}
+
 extern "C" {
 
 tdes_status tdes_key_schedule(const uint8_t key24[24], tdes_schedule *out) {
@@ -97,20 +111,22 @@ tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const v
     tdes_status st = check_buffers(d_in, d_out, nbytes);
     if (st != TDES_OK || nbytes == 0) return st;
 
-    tdes::RoundSequence seq;
-    tdes::round_sequence(*ks, dir, &seq);
     const uint8_t *in = static_cast<const uint8_t *>(d_in);
     uint8_t *out = static_cast<uint8_t *>(d_out);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
     if (kernel == TDES_KERNEL_SPBOX) {
+        tdes::RoundSequence seq;
+        tdes::round_sequence(*ks, dir, &seq);
         tdes::SpboxKeys k;
         tdes::spbox_keys(seq, &k);
         e = tdes::launch_spbox(k, in, out, nbytes, s);
-    } else {
+    } else if (kernel == TDES_KERNEL_BITSLICE) {
         tdes::BitsliceKeys k;
         tdes::bitslice_keys(*ks, dir, &k);
         e = tdes::launch_bitslice(k, in, out, nbytes, s);
+    } else {
+        e = tdes::launch_ecb_auto(*ks, dir, in, out, nbytes, s);
     }
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return TDES_OK;

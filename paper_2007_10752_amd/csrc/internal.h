@@ -128,6 +128,19 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
                           size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
                           uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
                           BatchConfig *best, float *best_us);
+// Bytes the table kernel covers with one block per lane in one wave of
+// resident workgroups on the current device (4 MiB on 256 CUs).  Up to this
+// size it has the lower latency: its lanes each run one block through the
+// rounds, while a bitsliced lane runs 32 (one launch of either kernel
+// measured 10-25 us against 33-35 us); above it the bitsliced kernel's
+// throughput wins.
+size_t spbox_one_pass_bytes();
+
+// tdes_ecb_crypt's TDES_KERNEL_AUTO: the table kernel up to
+// spbox_one_pass_bytes(), the bitsliced kernel above.
+hipError_t launch_ecb_auto(const tdes_schedule &ks, int dir, const uint8_t *in, uint8_t *out,
+                           size_t nbytes, hipStream_t stream);
+
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 

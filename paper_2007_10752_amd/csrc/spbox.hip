@@ -171,6 +171,8 @@ int resident_workgroups() {
 
 }  // namespace
 
+size_t spbox_one_pass_bytes() { return (size_t)resident_workgroups() * kThreads * 8; }
+
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream) {
     const size_t nblocks = nbytes / 8;

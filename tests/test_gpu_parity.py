@@ -143,6 +143,23 @@ def test_64mib_full(torch_dev, kernel, two_key):
     assert np.array_equal(rows, oracle.tdes_ecb(key, sample, decrypt=True))
 
 
+# The automatic kernel choice: the table kernel up to 4 MiB on a 256-CU
+# device (one block per lane, one wave of resident workgroups), the bitsliced
+# kernel above; sizes on both sides of that point, checked in full.
+AUTO_SIZES = [8, 32 << 10, (4 << 20) - 8, 4 << 20, (4 << 20) + 8, 8 << 20]
+
+
+@pytest.mark.parametrize("nbytes", AUTO_SIZES)
+def test_auto_kernel_choice(torch_dev, nbytes):
+    g = W.rng(W.SEED_BASE + 0x57)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, nbytes)
+    _say("auto", nbytes)
+    ct = _gpu(torch_dev, key, data, kernel="auto")
+    assert np.array_equal(ct, oracle.tdes_ecb(key, data))
+    assert np.array_equal(_gpu(torch_dev, key, ct, decrypt=True, kernel="auto"), data)
+
+
 # Sizes past the point where a lane takes several blocks of the grid-stride
 # loop (the table kernel at most 1,024 workgroups of 1,024 lanes: 2^20 blocks
 # per sweep), with remainders that leave lanes four, three, two or one block

@@ -338,7 +338,8 @@ tdes_status tdes_batch_config_save(const char *path, const char *device, uint32_
                                    const tdes_batch_config *cfg, double us_per_batch);
 
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
- * TDES_KERNEL_SPBOX; AUTO means the kernel AUTO selects) would receive for
+ * TDES_KERNEL_SPBOX; AUTO gives the bitsliced kernel's, its choice above
+ * the table kernel's one-pass size) would receive for
  * schedule ks and direction dir, copied to host memory `out` (cap bytes).
  * Returns the number of bytes written, or a negative tdes_status
  * (TDES_ERR_ARG for NULL pointers, bad enums or cap too small).  For

@@ -322,6 +322,26 @@ tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const voi
                                 size_t workspace_bytes, void *stream, int reps,
                                 tdes_batch_config *best);
 
+/* The autotuner for a stream of batches, run the way a server runs them:
+ * each configuration is timed over reps x n_streams
+ * back-to-back submits of this batch taking the n_streams lanes in turn,
+ * lane i writing d_out_bases[i] with workspace d_workspaces[i] on
+ * streams[i], so that batches on different streams overlap (one batch's
+ * last waves beside the next one's first).  The fastest configuration per
+ * batch is kept, saved and returned as by tdes_batch_autotune, which is this
+ * call with one lane.  Arrays of n_streams (1..8) host pointers; each
+ * output and workspace must not overlap another lane's, nor an output the
+ * input (TDES_ERR_OVERLAP); the other checks are tdes_batch_submit's, per
+ * lane.  Synchronous.  Errors: those of tdes_batch_autotune, and
+ * TDES_ERR_ARG for NULL arrays or n_streams outside 1..8. */
+tdes_status tdes_batch_autotune_streams(const tdes_msg *d_msgs, size_t n_msgs,
+                                        const void *d_schedules, size_t n_schedules,
+                                        const void *d_in_base, size_t in_bytes,
+                                        void *const *d_out_bases, size_t out_bytes,
+                                        void *const *d_workspaces, size_t workspace_bytes,
+                                        void *const *streams, int n_streams, int reps,
+                                        tdes_batch_config *best);
+
 /* The tuning cache file itself (host only, no device needed).  Load: the
  * entry for `device` (an architecture name such as "gfx950:sramecc+:xnack-")
  * and `cus` compute units from the JSON file at path into *out; returns 1

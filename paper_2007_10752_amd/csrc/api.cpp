@@ -322,26 +322,57 @@ tdes_status tdes_batch_autotune(const tdes_msg *d_msgs, size_t n_msgs, const voi
                                 void *d_out_base, size_t out_bytes, void *d_workspace,
                                 size_t workspace_bytes, void *stream, int reps,
                                 tdes_batch_config *best) {
+    void *outs[1] = {d_out_base}, *wss[1] = {d_workspace}, *streams[1] = {stream};
+    return tdes_batch_autotune_streams(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
+                                       in_bytes, outs, out_bytes, wss, workspace_bytes, streams, 1,
+                                       reps, best);
+}
+
+tdes_status tdes_batch_autotune_streams(const tdes_msg *d_msgs, size_t n_msgs,
+                                        const void *d_schedules, size_t n_schedules,
+                                        const void *d_in_base, size_t in_bytes,
+                                        void *const *d_out_bases, size_t out_bytes,
+                                        void *const *d_workspaces, size_t workspace_bytes,
+                                        void *const *streams, int n_streams, int reps,
+                                        tdes_batch_config *best) {
     g_last_error.clear();
     if (reps < 1 || best == nullptr) return fail(TDES_ERR_ARG, "reps must be >= 1 and best non-NULL");
+    if (n_streams < 1 || n_streams > tdes::kMaxTuneLanes)
+        return fail(TDES_ERR_ARG, "n_streams must be 1..%d", tdes::kMaxTuneLanes);
+    if (d_out_bases == nullptr || d_workspaces == nullptr || streams == nullptr)
+        return fail(TDES_ERR_ARG, "NULL lane array");
     if (n_msgs == 0) return fail(TDES_ERR_ARG, "nothing to tune on: no messages");
-    // same checks as tdes_batch_submit
-    tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules, d_in_base,
-                                              d_out_base, d_workspace, workspace_bytes);
-    if (st != TDES_OK) return st;
-    // every trial rewrites the output from the input: they must not alias,
-    // or each trial would encrypt the previous trial's result again
-    const uintptr_t a = (uintptr_t)d_in_base, b = (uintptr_t)d_out_base;
-    if (in_bytes > 0 && out_bytes > 0 && a < b + out_bytes && b < a + in_bytes)
-        return fail(TDES_ERR_OVERLAP,
-                    "autotuning runs the batch several times: input and output must not overlap");
+    tdes::TuneLane lanes[tdes::kMaxTuneLanes];
+    auto overlap = [](uintptr_t a, size_t na, uintptr_t b, size_t nb) {
+        return na > 0 && nb > 0 && a < b + nb && b < a + na;
+    };
+    for (int i = 0; i < n_streams; i++) {
+        // same checks as tdes_batch_submit, for every lane
+        tdes_status st = tdes_batch_submit_checks(d_msgs, n_msgs, d_schedules, n_schedules,
+                                                  d_in_base, d_out_bases[i], d_workspaces[i],
+                                                  workspace_bytes);
+        if (st != TDES_OK) return st;
+        // every trial rewrites the output from the input: they must not
+        // alias, or each trial would encrypt the previous trial's result again
+        if (overlap((uintptr_t)d_in_base, in_bytes, (uintptr_t)d_out_bases[i], out_bytes))
+            return fail(TDES_ERR_OVERLAP,
+                        "autotuning runs the batch several times: input and output must not overlap");
+        for (int j = 0; j < i; j++) {
+            // lanes run at the same time: their outputs and workspaces are their own
+            if (overlap((uintptr_t)d_out_bases[i], out_bytes, (uintptr_t)d_out_bases[j], out_bytes))
+                return fail(TDES_ERR_OVERLAP, "the lanes' outputs overlap");
+            if (overlap((uintptr_t)d_workspaces[i], workspace_bytes, (uintptr_t)d_workspaces[j],
+                        workspace_bytes))
+                return fail(TDES_ERR_OVERLAP, "the lanes' workspaces overlap");
+        }
+        lanes[i] = {static_cast<uint8_t *>(d_out_bases[i]), static_cast<uint64_t *>(d_workspaces[i]),
+                    static_cast<hipStream_t>(streams[i])};
+    }
     tdes::BatchConfig c;
     float us = 0;
     hipError_t e = tdes::batch_autotune(d_msgs, n_msgs, static_cast<const uint32_t *>(d_schedules),
                                         n_schedules, static_cast<const uint8_t *>(d_in_base),
-                                        in_bytes, static_cast<uint8_t *>(d_out_base), out_bytes,
-                                        static_cast<uint64_t *>(d_workspace),
-                                        static_cast<hipStream_t>(stream), reps, &c, &us);
+                                        in_bytes, lanes, n_streams, out_bytes, reps, &c, &us);
     if (e != hipSuccess) return fail(TDES_ERR_DEVICE, "autotune failed: %s", hipGetErrorString(e));
     best->kmax = (uint32_t)c.kmax;
     best->waves = (uint32_t)c.waves;

@@ -705,29 +705,42 @@ hipError_t launch_batch_prefixed(const tdes_msg *msgs, size_t n_msgs, const uint
 }
 
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
-                          size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
-                          uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
+                          size_t n_schedules, const uint8_t *in, uint64_t in_bytes,
+                          const TuneLane *lanes, int n_lanes, uint64_t out_bytes, int reps,
                           BatchConfig *best_out, float *best_us) {
+    if (n_lanes < 1 || n_lanes > kMaxTuneLanes) return hipErrorInvalidValue;
     BatchConfig keep;
     hipError_t e = batch_config_current(&keep);
     if (e != hipSuccess) return e;
     BatchConfig cands[64];
     const int n_cands = batch_config_list(cands, 64);
-    hipEvent_t a = nullptr, b = nullptr;
-    e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
+    // a: start, on lane 0's stream, which the other lanes wait for; end[i]:
+    // lane i's last batch, which lane 0 waits for before b
+    hipEvent_t a = nullptr, b = nullptr, end[kMaxTuneLanes] = {};
+    e = hipEventCreateWithFlags(&a, hipEventDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDefault);
+    for (int i = 1; i < n_lanes && e == hipSuccess; i++)
+        e = hipEventCreateWithFlags(&end[i], hipEventDisableTiming);
     float best_ms = 0;
     BatchConfig best = keep;
-    auto run = [&]() {
-        return launch_batch(msgs, n_msgs, schedules, n_schedules, in, in_bytes, out, out_bytes, ws,
-                            nullptr, stream);
+    auto run = [&](const TuneLane &l) {
+        return launch_batch(msgs, n_msgs, schedules, n_schedules, in, in_bytes, l.out, out_bytes,
+                            l.ws, nullptr, l.stream);
     };
+    const hipStream_t s0 = lanes[0].stream;
     for (int i = 0; i < n_cands && e == hipSuccess; i++) {
         e = batch_config_set(cands[i]);
-        if (e == hipSuccess) e = run();  // warm
-        if (e == hipSuccess) e = hipEventRecord(a, stream);
-        for (int r = 0; r < reps && e == hipSuccess; r++) e = run();
-        if (e == hipSuccess) e = hipEventRecord(b, stream);
+        for (int l = 0; l < n_lanes && e == hipSuccess; l++) e = run(lanes[l]);  // warm
+        for (int l = 0; l < n_lanes && e == hipSuccess; l++) e = hipStreamSynchronize(lanes[l].stream);
+        if (e == hipSuccess) e = hipEventRecord(a, s0);
+        for (int l = 1; l < n_lanes && e == hipSuccess; l++) e = hipStreamWaitEvent(lanes[l].stream, a, 0);
+        // back-to-back batches, taking the lanes in turn
+        for (int r = 0; r < reps * n_lanes && e == hipSuccess; r++) e = run(lanes[r % n_lanes]);
+        for (int l = 1; l < n_lanes && e == hipSuccess; l++) {
+            e = hipEventRecord(end[l], lanes[l].stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s0, end[l], 0);
+        }
+        if (e == hipSuccess) e = hipEventRecord(b, s0);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
@@ -739,9 +752,11 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
     (void)batch_config_set(e == hipSuccess ? best : keep);
     if (a != nullptr) (void)hipEventDestroy(a);
     if (b != nullptr) (void)hipEventDestroy(b);
+    for (int l = 1; l < n_lanes; l++)
+        if (end[l] != nullptr) (void)hipEventDestroy(end[l]);
     if (e == hipSuccess) {
         *best_out = best;
-        *best_us = best_ms * 1e3f / (float)reps;
+        *best_us = best_ms * 1e3f / (float)(reps * n_lanes);
     }
     return e;
 }

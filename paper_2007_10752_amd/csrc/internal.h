@@ -120,13 +120,22 @@ hipError_t launch_batch(const tdes_msg *msgs, size_t n_msgs, const uint32_t *sch
 // current device (its address, looked up on the first call on that device,
 // and its size in bytes).
 hipError_t noalloc_workspace(uint64_t **ws, size_t *ws_bytes);
-// Times the batch (scan + cipher, `reps` runs after one warm run) in every
-// configuration on `stream`, keeps the fastest for later batched launches
-// on the current device and returns it with its time per batch (us).
-// Synchronous.
+// One lane of the autotuner: an output buffer, a workspace and a stream of
+// its own.
+struct TuneLane {
+    uint8_t *out;
+    uint64_t *ws;
+    hipStream_t stream;
+};
+constexpr int kMaxTuneLanes = 8;
+// Times the batch (scan + cipher) in every configuration: after one warm run
+// per lane, reps x n_lanes back-to-back submits taking the lanes in turn
+// (with one lane, on one stream; with several, batches overlap across the
+// lanes' streams).  Keeps the fastest for later batched launches on the
+// current device and returns it with its time per batch (us).  Synchronous.
 hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *schedules,
-                          size_t n_schedules, const uint8_t *in, uint64_t in_bytes, uint8_t *out,
-                          uint64_t out_bytes, uint64_t *ws, hipStream_t stream, int reps,
+                          size_t n_schedules, const uint8_t *in, uint64_t in_bytes,
+                          const TuneLane *lanes, int n_lanes, uint64_t out_bytes, int reps,
                           BatchConfig *best, float *best_us);
 // Bytes the table kernel covers with one block per lane in one wave of
 // resident workgroups on the current device (4 MiB on 256 CUs).  Up to this

@@ -29,7 +29,7 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_server_release", "tdes_server_release_many", "tdes_server_get_stats",
            "tdes_server_now", "tdes_ecb_host",
            "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_paper_design",
-           "tdes_batch_autotune", "tdes_batch_get_config",
+           "tdes_batch_autotune", "tdes_batch_autotune_streams", "tdes_batch_get_config",
            "tdes_batch_set_config", "tdes_batch_config_load", "tdes_batch_config_save")
 
 DEVICE_SCHEDULE_BYTES = 800
@@ -107,6 +107,10 @@ def lib():
         L.tdes_batch_autotune.argtypes = [vp, sz, vp, sz, vp, sz, vp, sz, vp, sz, vp,
                                           ctypes.c_int, cfg_p]
         L.tdes_batch_autotune.restype = ctypes.c_int
+        vpp = ctypes.POINTER(ctypes.c_void_p)
+        L.tdes_batch_autotune_streams.argtypes = [vp, sz, vp, sz, vp, sz, vpp, sz, vpp, sz, vpp,
+                                                  ctypes.c_int, ctypes.c_int, cfg_p]
+        L.tdes_batch_autotune_streams.restype = ctypes.c_int
         L.tdes_batch_get_config.argtypes = [cfg_p]
         L.tdes_batch_get_config.restype = ctypes.c_int
         L.tdes_batch_set_config.argtypes = [cfg_p]
@@ -476,6 +480,30 @@ class Batch:
             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
             ctypes.c_void_p(_stream_handle(stream) if stream is not None else self.stream),
             int(reps), ctypes.byref(c)))
+        return c.as_dict()
+
+    def autotune_streams(self, x, outs, streams, reps=3):
+        """The autotuner for a stream of these batches over several streams
+        (tdes_batch_autotune_streams): lane i writes outs[i] on streams[i]
+        (torch streams) with a workspace of its own; returns the kept
+        configuration as a dict (synchronous).  The outputs must not overlap
+        x or each other."""
+        import torch
+        n = len(outs)
+        if n != len(streams) or n < 1:
+            raise ValueError("one output per stream")
+        wss = [self.ws] + [torch.empty_like(self.ws) for _ in range(n - 1)]
+        arr = lambda v: (ctypes.c_void_p * n)(*[ctypes.c_void_p(p) for p in v])
+        c = BatchConfig()
+        size = outs[0].numel()
+        if any(o.numel() != size for o in outs):
+            raise ValueError("outputs of one size")
+        _check(lib().tdes_batch_autotune_streams(
+            ctypes.c_void_p(self.msgs.data_ptr()), self.n_msgs,
+            ctypes.c_void_p(self.sched.data_ptr()), self.n_sched, ctypes.c_void_p(x.data_ptr()),
+            x.numel(), arr([o.data_ptr() for o in outs]), size,
+            arr([w.data_ptr() for w in wss]), self.ws_bytes,
+            arr([_stream_handle(st) for st in streams]), n, int(reps), ctypes.byref(c)))
         return c.as_dict()
 
     def skipped(self):

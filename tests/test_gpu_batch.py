@@ -427,6 +427,34 @@ def test_batch_autotune_keeps_results(torch_dev):
         assert np.array_equal(want[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
 
 
+def test_batch_autotune_streams_keeps_results(torch_dev):
+    # The stream-of-batches autotuner runs the batch on two streams at once,
+    # each lane into its own output with its own workspace: both outputs hold
+    # the batch's bytes, and the kept configuration is the current one.
+    torch = torch_dev
+    g = W.rng(W.SEED_BASE + 0x30D)
+    n = 300
+    lengths = (g.integers(0, 300, size=n) * 8).astype(np.int64)
+    keys = W.key_bundles(g, n)
+    dirs = g.integers(0, 2, size=n)
+    data = W.uniform_bytes(g, int(lengths.sum()))
+    offs, want, b = _run_batch(torch, keys, lengths, dirs, data)
+    x = torch.from_numpy(data).cuda()
+    outs = [torch.full_like(x, 0xA5), torch.full_like(x, 0x5A)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    _say("batch autotune, two streams")
+    m = b.autotune_streams(x, outs, streams, reps=2)
+    assert m["grid_mult"] in (1, 2, 3, 4) and m["kmax"] in (4, 8, 16) and m["waves"] in (3, 4, 5)
+    cur = T.batch_get_config()
+    assert (cur["kmax"], cur["waves"], cur["grid_mult"]) == (m["kmax"], m["waves"], m["grid_mult"])
+    torch.cuda.synchronize()
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), want)
+    for i in range(0, n, 37):
+        seg = slice(int(offs[i]), int(offs[i] + lengths[i]))
+        assert np.array_equal(want[seg], oracle.tdes_ecb(keys[i], data[seg], bool(dirs[i]))), i
+
+
 def test_out_of_range_messages_are_skipped(torch_dev):
     # Message ranges are checked against the input and output buffer sizes:
     # a message reaching past either end (including offsets that would wrap

@@ -164,6 +164,33 @@ def test_batch_autotune_argument_errors():
     assert call(d_in=0x200800) == -4    # output range covers the input's start
 
 
+def test_batch_autotune_streams_argument_errors():
+    lib = T.lib()
+    m = T.BatchConfig()
+    a = ctypes.c_void_p(0x1000)
+
+    def arr(*v):
+        return (ctypes.c_void_p * len(v))(*[ctypes.c_void_p(x) for x in v])
+
+    def call(outs=(0x200000, 0x300000), wss=(0x1000, 0x400000), n=2, null=None, d_in=0x100000):
+        o = None if null == "outs" else arr(*outs)
+        w = None if null == "wss" else arr(*wss)
+        st = None if null == "streams" else arr(*([0] * max(1, n)))
+        return lib.tdes_batch_autotune_streams(a, 4, a, 1, ctypes.c_void_p(d_in), 4096, o, 4096,
+                                               w, 1 << 16, st, n, 2, ctypes.byref(m))
+    assert call(n=0) == -1
+    assert call(n=9, outs=[0x200000 + 0x2000 * i for i in range(9)],
+                wss=[0x1000000 + 0x20000 * i for i in range(9)]) == -1
+    for what in ("outs", "wss", "streams"):
+        assert call(null=what) == -1, what
+    assert call(outs=(0x200000, 0x200800)) == -4      # the lanes' outputs overlap
+    assert b"outputs overlap" in lib.tdes_last_error()
+    assert call(wss=(0x1000, 0x8000)) == -4            # the lanes' workspaces overlap
+    assert b"workspaces overlap" in lib.tdes_last_error()
+    assert call(outs=(0x200000, 0x100000)) == -4       # a lane writes over the input
+    assert call(wss=(0x1000, 0x400004)) == -3          # misaligned workspace
+
+
 def test_batch_submit_argument_errors():
     lib = T.lib()
     a = ctypes.c_void_p(0x1000)

@@ -194,6 +194,17 @@ def second_use_plan(nets):
         opts = [frozenset(c) for n in range(len(qs) + 1)
                 for c in itertools.combinations(qs, n) if foldable(nets[box], c)]
         options.append(opts)
+    # each box has a handful of fold options at most (a fold needs a free
+    # operand in every gate that reads the input); keep the search bounded
+    # all the same by dropping the smaller options of the widest boxes
+    while True:
+        size = 1
+        for o in options:
+            size *= len(o)
+        if size <= 1 << 20:
+            break
+        widest = max(range(8), key=lambda b: len(options[b]))
+        options[widest] = sorted(options[widest], key=len)[len(options[widest]) // 2:]
     best, best_key = None, None
     for choice in itertools.product(*options):
         fold_e = {6 * box + q for box, c in enumerate(choice) for q in c}

@@ -127,9 +127,18 @@ __device__ __forceinline__ void blocks(const uint8_t *in, uint8_t *out, size_t b
 
 __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in, uint8_t *out,
                                                              size_t nblocks, SpboxKeys keys) {
-    __shared__ uint32_t table[kTableWords];
+    __shared__ __align__(16) uint32_t table[kTableWords];
     __shared__ uint4 rk[48];
-    for (int i = threadIdx.x; i < kTableWords; i += kThreads) table[i] = SP_TABLE[i / kCopies];
+    // 512 entries x 32 copies: each pair of lanes writes one entry's copies,
+    // 16 each as four 16-byte stores, after one load of the entry
+    static_assert(kTableWords == 2 * kThreads * 8 && kCopies == 32, "table fill layout");
+    {
+        const int e = threadIdx.x >> 1, half = threadIdx.x & 1;
+        const uint32_t v = SP_TABLE[e];
+        uint4 *dst = reinterpret_cast<uint4 *>(table + e * kCopies + half * 16);
+        const uint4 q = make_uint4(v, v, v, v);
+        dst[0] = q; dst[1] = q; dst[2] = q; dst[3] = q;
+    }
     if (threadIdx.x < 48) {
         const int r = threadIdx.x;
         rk[r] = make_uint4(keys.w[r][0], keys.w[r][1], keys.w[r][2], keys.w[r][3]);

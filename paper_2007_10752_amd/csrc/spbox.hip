@@ -129,15 +129,15 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in,
                                                              size_t nblocks, SpboxKeys keys) {
     __shared__ __align__(16) uint32_t table[kTableWords];
     __shared__ uint4 rk[48];
-    // 512 entries x 32 copies: each pair of lanes writes one entry's copies,
-    // 16 each as four 16-byte stores, after one load of the entry
-    static_assert(kTableWords == 2 * kThreads * 8 && kCopies == 32, "table fill layout");
-    {
-        const int e = threadIdx.x >> 1, half = threadIdx.x & 1;
-        const uint32_t v = SP_TABLE[e];
-        uint4 *dst = reinterpret_cast<uint4 *>(table + e * kCopies + half * 16);
-        const uint4 q = make_uint4(v, v, v, v);
-        dst[0] = q; dst[1] = q; dst[2] = q; dst[3] = q;
+    // the 512 entries x 32 copies as 16-byte chunks (8 per entry), lane i
+    // writing chunks i, i + 1024, ...: each store of a wave covers 1 KiB in a
+    // row, free of bank conflicts
+    static_assert(kTableWords == 4 * 4 * kThreads && kCopies == 32, "table fill layout");
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int c = threadIdx.x + j * kThreads;
+        const uint32_t v = SP_TABLE[c >> 3];
+        reinterpret_cast<uint4 *>(table)[c] = make_uint4(v, v, v, v);
     }
     if (threadIdx.x < 48) {
         const int r = threadIdx.x;

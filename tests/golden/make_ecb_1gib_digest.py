@@ -9,7 +9,7 @@ Calls only the oracle and the seeded input generators:
 
 takes about a minute on 8 host threads.  The GPU test compares the digest of
 the GPU's full output with the one stored here, so all 134,217,728 blocks are
-checked without running the oracle on the GPU machine.
+checked without a full oracle run at test time.
 """
 import hashlib
 import os

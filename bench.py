@@ -216,7 +216,7 @@ def c1_section():
             "host_calls_GBps": round(n / t_host / 1e9, 3),
             "host_us_per_call": round(t_host * 1e6, 2),
             "frac": frac_of_peak("spbox", n, t_enc),
-            "kernel": "automatic choice: the table kernel at this size",
+            "kernel": "automatic choice: %s" % tdes.auto_kernel(n),
             "bitsliced_encrypt_us": round(t_enc_bs * 1e6, 2),
             "bitsliced_encrypt_GBps": round(n / t_enc_bs / 1e9, 3),
             "bit_exact_vs_oracle_and_round_trip": ok, "launches": 200, "stat": "median",

@@ -64,6 +64,13 @@ typedef enum {
     TDES_KERNEL_SPBOX = 2     /* one block per lane; S-box+P tables in LDS */
 } tdes_kernel;
 
+/* The kernel TDES_KERNEL_AUTO runs for nbytes on the current device:
+ * TDES_KERNEL_SPBOX up to the table kernel's one-pass size (resident
+ * workgroups x 1,024 lanes x 8 bytes: 4 MiB on 256 CUs), TDES_KERNEL_BITSLICE
+ * above.  Returns a negative tdes_status (TDES_ERR_DEVICE) without a
+ * device. */
+int tdes_ecb_auto_kernel(size_t nbytes);
+
 /* Round keys of a key bundle, Sec. III-A.  k[b][i] is round key i+1 (of 16)
  * of base key K(b+1), 48 bits, with round-key bit 1 as bit 47 of the value.
  * A plain value type: copy it, keep it on the host. */

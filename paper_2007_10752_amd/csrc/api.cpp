@@ -78,9 +78,13 @@ tdes_status tdes::set_last_error(tdes_status st, const char *msg) {
     return st;
 }
 
+int tdes::auto_kernel(size_t nbytes) {
+    return nbytes <= spbox_one_pass_bytes() ? TDES_KERNEL_SPBOX : TDES_KERNEL_BITSLICE;
+}
+
 hipError_t tdes::launch_ecb_auto(const tdes_schedule &ks, int dir, const uint8_t *in,
                                  uint8_t *out, size_t nbytes, hipStream_t stream) {
-    if (nbytes <= spbox_one_pass_bytes()) {
+    if (auto_kernel(nbytes) == TDES_KERNEL_SPBOX) {
         RoundSequence seq;
         round_sequence(ks, dir, &seq);
         SpboxKeys k;
@@ -99,6 +103,13 @@ tdes_status tdes_key_schedule(const uint8_t key24[24], tdes_schedule *out) {
     if (key24 == nullptr || out == nullptr) return fail(TDES_ERR_ARG, "NULL key or schedule");
     for (int b = 0; b < 3; b++) tdes::des_round_keys(key24 + 8 * b, out->k[b]);  // Sec. III-A
     return TDES_OK;
+}
+
+int tdes_ecb_auto_kernel(size_t nbytes) {
+    g_last_error.clear();
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(TDES_ERR_DEVICE, "no device");
+    return tdes::auto_kernel(nbytes);
 }
 
 tdes_status tdes_ecb_crypt(const tdes_schedule *ks, int dir, int kernel, const void *d_in,

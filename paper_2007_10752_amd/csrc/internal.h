@@ -146,7 +146,9 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
 size_t spbox_one_pass_bytes();
 
 // tdes_ecb_crypt's TDES_KERNEL_AUTO: the table kernel up to
-// spbox_one_pass_bytes(), the bitsliced kernel above.
+// spbox_one_pass_bytes(), the bitsliced kernel above (auto_kernel says which,
+// as a tdes_kernel value).
+int auto_kernel(size_t nbytes);
 hipError_t launch_ecb_auto(const tdes_schedule &ks, int dir, const uint8_t *in, uint8_t *out,
                            size_t nbytes, hipStream_t stream);
 

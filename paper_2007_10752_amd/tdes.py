@@ -30,6 +30,7 @@ SYMBOLS = ("tdes_key_schedule", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ec
            "tdes_server_now", "tdes_ecb_host",
            "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_paper_design",
            "tdes_batch_autotune", "tdes_batch_autotune_streams", "tdes_batch_get_config",
+           "tdes_ecb_auto_kernel",
            "tdes_batch_set_config", "tdes_batch_config_load", "tdes_batch_config_save")
 
 DEVICE_SCHEDULE_BYTES = 800
@@ -111,6 +112,8 @@ def lib():
         L.tdes_batch_autotune_streams.argtypes = [vp, sz, vp, sz, vp, sz, vpp, sz, vpp, sz, vpp,
                                                   ctypes.c_int, ctypes.c_int, cfg_p]
         L.tdes_batch_autotune_streams.restype = ctypes.c_int
+        L.tdes_ecb_auto_kernel.argtypes = [sz]
+        L.tdes_ecb_auto_kernel.restype = ctypes.c_int
         L.tdes_batch_get_config.argtypes = [cfg_p]
         L.tdes_batch_get_config.restype = ctypes.c_int
         L.tdes_batch_set_config.argtypes = [cfg_p]
@@ -162,6 +165,15 @@ def ecb_crypt_ptr(schedule, direction, kernel, d_in, d_out, nbytes, stream=0):
     _check(lib().tdes_ecb_crypt(ctypes.byref(schedule), int(direction), int(kernel),
                                 ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
                                 ctypes.c_size_t(nbytes), ctypes.c_void_p(stream)))
+
+
+def auto_kernel(nbytes):
+    """The kernel TDES_KERNEL_AUTO runs for nbytes on the current device, by
+    name ("spbox" or "bitslice")."""
+    k = lib().tdes_ecb_auto_kernel(int(nbytes))
+    if k < 0:
+        raise TdesError(k, lib().tdes_last_error().decode())
+    return {KERNEL_BITSLICE: "bitslice", KERNEL_SPBOX: "spbox"}[k]
 
 
 def kernel_key_bytes(schedule, direction, kernel):

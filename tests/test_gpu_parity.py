@@ -149,6 +149,17 @@ def test_64mib_full(torch_dev, kernel, two_key):
 AUTO_SIZES = [8, 32 << 10, (4 << 20) - 8, 4 << 20, (4 << 20) + 8, 8 << 20]
 
 
+def test_auto_kernel_query(torch_dev):
+    # the table kernel up to one pass of its resident workgroups (2 per CU,
+    # 1,024 lanes, one 8-byte block each), the bitsliced kernel above
+    cus = torch_dev.cuda.get_device_properties(0).multi_processor_count
+    limit = 2 * cus * 1024 * 8
+    assert T.auto_kernel(8) == "spbox"
+    assert T.auto_kernel(limit) == "spbox"
+    assert T.auto_kernel(limit + 8) == "bitslice"
+    assert T.auto_kernel(1 << 30) == "bitslice"
+
+
 @pytest.mark.parametrize("nbytes", AUTO_SIZES)
 def test_auto_kernel_choice(torch_dev, nbytes):
     g = W.rng(W.SEED_BASE + 0x57)

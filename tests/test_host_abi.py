@@ -164,6 +164,14 @@ def test_batch_autotune_argument_errors():
     assert call(d_in=0x200800) == -4    # output range covers the input's start
 
 
+def test_auto_kernel_query_needs_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present: the GPU tests cover the query")
+    assert T.lib().tdes_ecb_auto_kernel(8) == -6
+    assert b"no device" in T.lib().tdes_last_error()
+
+
 def test_batch_autotune_streams_argument_errors():
     lib = T.lib()
     m = T.BatchConfig()

@@ -34,6 +34,8 @@ constexpr int kDirWords = 100;
 
 TDES_HD inline uint64_t ks_gather(uint64_t in, int nin, const uint8_t *table, int nout) {
     uint64_t out = 0;
+    // unrolled where nout is a constant: the table entries become shift counts
+#pragma unroll
     for (int j = 0; j < nout; j++) out = (out << 1) | ((in >> (nin - table[j])) & 1u);
     return out;
 }
@@ -134,6 +136,9 @@ template <class F>
 TDES_HD inline void bs_mask_walk(const uint32_t *P, F &&f, uint32_t extra[4]) {
     uint32_t mx = 0, my = P[0];  // current mask of each half
     extra[0] = my;
+    // unrolled: the half each round writes and its next reader are then
+    // constants, and the walk is a straight line of selects and XORs
+#pragma unroll
     for (int t = 0; t < 48; t++) {
         const bool dx = bs_dest_is_x(t);
         uint32_t &ms = dx ? my : mx;

@@ -74,9 +74,14 @@ def test_mixed_equals_alone_and_oracle(env, mode):
     trace = W.serving_trace(W.SEED_BASE + 5, rate=100000, duration_s=0.03, bands=SMALL_BANDS)
     reqs = S.make_requests(trace, pool.data_ptr(), pool.numel(), W.SEED_BASE + 6)
     n = len(reqs)
+    # the first 64 arrive together: they queue before the first launch and
+    # share one batch whatever the host's speed, so batch-kernel output is
+    # always among the checked results
+    arrival = trace["arrival"].copy()
+    arrival[:64] = 0.0
     _say("serve mix mode", mode, n, "requests")
     srv = _server(env, mode=mode, slots=4, max_batch_msgs=1024)
-    got, lat, status, st, batch_of = _run(env, srv, reqs, trace["arrival"], None)
+    got, lat, status, st, batch_of = _run(env, srv, reqs, arrival, None)
     srv.close()
     assert (status == 0).all()
     assert st["completed"] == n and st["released"] == n and st["in_flight_bytes"] == 0
@@ -98,6 +103,7 @@ def test_mixed_equals_alone_and_oracle(env, mode):
     if mode == S.BATCHED:
         assert st["batches"] < n                 # requests really were batched
         assert len(shared) >= 40, len(shared)    # and the check covers batch-kernel output
+    _say("serve mix shared/few/single", len(shared), len(few), len(single))
     alone = _server(env, mode=S.BATCHED, slots=1, max_batch_msgs=1)
     for t in sorted(capture):
         one, _, st1, _, _ = _run(env, alone, reqs[t:t + 1], np.zeros(1), {0})

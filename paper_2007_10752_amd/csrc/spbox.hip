@@ -125,8 +125,11 @@ __device__ __forceinline__ void blocks(const uint8_t *in, uint8_t *out, size_t b
     }
 }
 
+// `per`: lanes of each workgroup that take blocks (a multiple of 64, at most
+// kThreads); all kThreads lanes fill the tables, then the others exit.
 __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in, uint8_t *out,
-                                                             size_t nblocks, SpboxKeys keys) {
+                                                             size_t nblocks, uint32_t per,
+                                                             SpboxKeys keys) {
     __shared__ __align__(16) uint32_t table[kTableWords];
     __shared__ uint4 rk[48];
     // the 512 entries x 32 copies as 16-byte chunks (8 per entry), lane i
@@ -144,14 +147,15 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in,
         rk[r] = make_uint4(keys.w[r][0], keys.w[r][1], keys.w[r][2], keys.w[r][3]);
     }
     __syncthreads();
+    if (threadIdx.x >= per) return;  // whole waves: per is a multiple of 64
     const uint8_t *sp = reinterpret_cast<const uint8_t *>(table);
     const uint32_t lane = (threadIdx.x % kCopies) * 4u;
     const uint32_t mask = in_vgpr(kIndexMask);
 
     // Grid-stride over blocks: four at a time while this thread has four,
     // then two, then one.
-    const size_t stride = (size_t)gridDim.x * kThreads;
-    size_t b = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * per;
+    size_t b = (size_t)blockIdx.x * per + threadIdx.x;
     for (; b + 3 * stride < nblocks; b += 4 * stride) blocks<4>(in, out, b, stride, sp, lane, mask, rk);
     for (; b + stride < nblocks; b += 2 * stride) blocks<2>(in, out, b, stride, sp, lane, mask, rk);
     if (b < nblocks) blocks<1>(in, out, b, stride, sp, lane, mask, rk);
@@ -185,13 +189,20 @@ size_t spbox_one_pass_bytes() { return (size_t)resident_workgroups() * kThreads 
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream) {
     const size_t nblocks = nbytes / 8;
-    size_t grid = (nblocks + kThreads - 1) / kThreads;
+    // Few blocks: fewer working lanes per workgroup and more workgroups, so
+    // that the blocks spread over as many CUs as there are (one workgroup
+    // each) rather than crowding a few CUs' LDS: the smallest per in 64,
+    // 128, .. 1024 whose workgroups fit the CUs once.
+    const size_t cus = (size_t)resident_workgroups() / 2;
+    uint32_t per = 64;
+    while (per < (uint32_t)kThreads && (nblocks + per - 1) / per > cus) per *= 2;
+    size_t grid = (nblocks + per - 1) / per;
     // Two workgroups per resident slot: the second wave of workgroups fills
     // the slots of those that finish early.
     const size_t cap = 2 * (size_t)resident_workgroups();
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL(tdes_spbox_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, in,
-                       out, nblocks, k);
+                       out, nblocks, per, k);
     return hipGetLastError();
 }
 

@@ -171,6 +171,24 @@ def test_auto_kernel_choice(torch_dev, nbytes):
     assert np.array_equal(_gpu(torch_dev, key, ct, decrypt=True, kernel="auto"), data)
 
 
+# The table kernel spreads few blocks over the CUs with 64, 128, .. 1,024
+# working lanes per workgroup (the fewest whose workgroups fit the CUs once):
+# block counts at and just past each switch (CUs x lanes), and one between,
+# in full against the oracle, both directions.
+@pytest.mark.parametrize("lanes,extra", [(64, 0), (64, 1), (96, 37), (128, 0), (128, 1),
+                                         (256, 0), (256, 1), (512, 0), (512, 1)])
+def test_table_kernel_spread(torch_dev, lanes, extra):
+    cus = torch_dev.cuda.get_device_properties(0).multi_processor_count
+    nblk = cus * lanes + extra
+    g = W.rng(W.SEED_BASE + 0x5A)
+    key = W.key_bundle(g)
+    data = W.uniform_bytes(g, 8 * nblk)
+    _say("table spread", nblk)
+    ct = _gpu(torch_dev, key, data, kernel="spbox")
+    assert np.array_equal(ct, oracle.tdes_ecb(key, data))
+    assert np.array_equal(_gpu(torch_dev, key, ct, decrypt=True, kernel="spbox"), data)
+
+
 # Sizes past the point where a lane takes several blocks of the grid-stride
 # loop (the table kernel at most 1,024 workgroups of 1,024 lanes: 2^20 blocks
 # per sweep), with remainders that leave lanes four, three, two or one block

@@ -155,6 +155,27 @@ hipError_t launch_ecb_auto(const tdes_schedule &ks, int dir, const uint8_t *in, 
 hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, size_t nbytes,
                         hipStream_t stream);
 
+// The table kernel over several messages in one launch, each with its own
+// keys (the request server's small batches).  Message i's blocks go to
+// workgroups first_wg .. first_wg + ceil(nblocks / per) - 1, `per` blocks
+// each; first_wg of message 0 is 0 and the values do not decrease.
+struct SpboxMsg {
+    const uint8_t *in;
+    uint8_t *out;
+    uint64_t nblocks;
+    uint32_t first_wg;
+    uint32_t pad;
+};
+constexpr uint32_t kSpboxMultiMax = 64;  // messages per launch
+// Working lanes per workgroup for messages of these block counts: the fewest
+// of 64, 128, .. 1,024 whose workgroups fit the CUs once (1,024 if none).
+uint32_t spbox_multi_lanes(const uint64_t *nblocks, size_t n);
+// d_msgs: n device descriptors (1 <= n <= kSpboxMultiMax); d_keys: n
+// SpboxKeys in device memory, 16-byte aligned; n_wg: the workgroups the
+// descriptors cover (first_wg + ceil(nblocks / per) of the last message).
+hipError_t launch_spbox_multi(const SpboxMsg *d_msgs, uint32_t n, const SpboxKeys *d_keys,
+                              uint32_t per, uint32_t n_wg, hipStream_t stream);
+
 // One DES pass of the one-thread-per-bit comparison kernel (in may equal out).
 hipError_t launch_replica_pass(const ReplicaKeyBits &k, const uint8_t *in, uint8_t *out,
                                size_t nbytes, hipStream_t stream);

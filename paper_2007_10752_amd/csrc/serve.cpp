@@ -20,6 +20,16 @@ constexpr int kPlainEvents = 4096;
 // three small requests take ~10 us each back to back, before the copy, scan
 // and batched kernel (~45 us) would finish.
 constexpr size_t kPlainBatchMax = 3;
+// Larger batches of at most this many requests and this many bytes in all
+// run as one launch of the table kernel over the requests (one block per
+// lane, each request's round keys built on the host), which finishes well
+// before the batched bitsliced path, whose lanes run 32 blocks each.
+constexpr size_t kTableBatchMax = tdes::kSpboxMultiMax;
+// Its staging area: descriptors, then round keys (one pinned host buffer
+// mirrored by one device buffer, so a batch needs a single copy).
+constexpr size_t kTabKeysOff = kTableBatchMax * sizeof(tdes::SpboxMsg);
+constexpr size_t kTabBytes = kTabKeysOff + kTableBatchMax * sizeof(tdes::SpboxKeys);
+static_assert(kTabKeysOff % 16 == 0, "round keys 16-byte aligned");
 
 double now_s() {
     using namespace std::chrono;
@@ -100,6 +110,7 @@ struct Slot {
     Staging lay;
     uint8_t *h_stage = nullptr, *d_stage = nullptr;
     uint32_t *d_sched = nullptr;
+    uint8_t *h_tab = nullptr, *d_tab = nullptr;  // table-kernel batches
 };
 
 struct PlainEntry {
@@ -235,6 +246,40 @@ tdes_status launch_slot(tdes_server *s, Slot &sl) {
                                       a.req.nbytes, sl.stream);
             if (e != hipSuccess) break;
         }
+        if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+        return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
+    }
+    uint64_t batch_bytes = 0;
+    for (const Active &a : sl.reqs) batch_bytes += a.req.nbytes;
+    if (n <= kTableBatchMax && batch_bytes <= tdes::spbox_one_pass_bytes()) {
+        tdes::SpboxMsg *tm = reinterpret_cast<tdes::SpboxMsg *>(sl.h_tab);
+        tdes::SpboxKeys *tk = reinterpret_cast<tdes::SpboxKeys *>(sl.h_tab + kTabKeysOff);
+        uint64_t nb[kTableBatchMax];
+        for (size_t i = 0; i < n; i++) nb[i] = sl.reqs[i].req.nbytes / 8;
+        const uint32_t per = tdes::spbox_multi_lanes(nb, n);
+        uint64_t wg = 0;
+        for (size_t i = 0; i < n; i++) {
+            const Active &a = sl.reqs[i];
+            tdes_schedule ks;
+            for (int b = 0; b < 3; b++) tdes::des_round_keys(a.req.key24 + 8 * b, ks.k[b]);
+            tdes::RoundSequence seq;
+            tdes::round_sequence(ks, (int)a.req.dir, &seq);
+            tdes::spbox_keys(seq, &tk[i]);
+            tm[i].in = static_cast<const uint8_t *>(a.req.d_in);
+            tm[i].out = static_cast<uint8_t *>(s->cfg.d_arena) + a.out_off;
+            tm[i].nblocks = nb[i];
+            tm[i].first_wg = (uint32_t)wg;
+            tm[i].pad = 0;
+            wg += (nb[i] + per - 1) / per;
+        }
+        // (the tail of the descriptor area is copied too: it is small)
+        e = hipMemcpyAsync(sl.d_tab, sl.h_tab, kTabKeysOff + n * sizeof(tdes::SpboxKeys),
+                           hipMemcpyHostToDevice, sl.stream);
+        if (e == hipSuccess)
+            e = tdes::launch_spbox_multi(
+                reinterpret_cast<const tdes::SpboxMsg *>(sl.d_tab), (uint32_t)n,
+                reinterpret_cast<const tdes::SpboxKeys *>(sl.d_tab + kTabKeysOff), per,
+                (uint32_t)wg, sl.stream);
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
         return e == hipSuccess ? TDES_OK : fail(TDES_ERR_DEVICE, hipGetErrorString(e));
     }
@@ -385,6 +430,8 @@ void free_device(tdes_server *s) {
         if (sl.h_stage) (void)hipHostFree(sl.h_stage);
         if (sl.d_stage) (void)hipFree(sl.d_stage);
         if (sl.d_sched) (void)hipFree(sl.d_sched);
+        if (sl.h_tab) (void)hipHostFree(sl.h_tab);
+        if (sl.d_tab) (void)hipFree(sl.d_tab);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
@@ -432,6 +479,8 @@ tdes_status tdes_server_create(const tdes_server_config *cfg, tdes_server **out)
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_stage, sl.lay.bytes, 0);
             if (e == hipSuccess) e = hipMalloc((void **)&sl.d_stage, sl.lay.bytes);
             if (e == hipSuccess) e = hipMalloc((void **)&sl.d_sched, n * TDES_DEVICE_SCHEDULE_BYTES);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_tab, kTabBytes, 0);
+            if (e == hipSuccess) e = hipMalloc((void **)&sl.d_tab, kTabBytes);
         }
     }
     if (e != hipSuccess) {

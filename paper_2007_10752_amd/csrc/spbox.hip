@@ -161,6 +161,41 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_kernel(const uint8_t *in,
     if (b < nblocks) blocks<1>(in, out, b, stride, sp, lane, mask, rk);
 }
 
+// Several messages, each with its own keys: workgroup g takes up to `per`
+// blocks of the message whose workgroup range holds g (one block per
+// working lane), after filling its tables and copying that message's round
+// keys.  n <= 64, so one ballot over the messages' first workgroups finds
+// the message: they do not decrease and the first is 0, so the lanes whose
+// entry is at or before g are a prefix, and the last of them is the message
+// (an empty message shares its first workgroup with the next one).
+__global__ __launch_bounds__(kThreads) void tdes_spbox_multi_kernel(const SpboxMsg *msgs,
+                                                                   uint32_t n,
+                                                                   const SpboxKeys *keys,
+                                                                   uint32_t per) {
+    static_assert(kSpboxMultiMax <= 64, "one ballot covers the messages");
+    __shared__ __align__(16) uint32_t table[kTableWords];
+    __shared__ uint4 rk[48];
+    const uint32_t g = blockIdx.x;
+    const uint32_t l64 = threadIdx.x % 64;
+    const bool le = l64 < n && msgs[l64].first_wg <= g;
+    const uint32_t m = (uint32_t)__popcll(__ballot(le)) - 1u;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int c = threadIdx.x + j * kThreads;
+        const uint32_t v = SP_TABLE[c >> 3];
+        reinterpret_cast<uint4 *>(table)[c] = make_uint4(v, v, v, v);
+    }
+    if (threadIdx.x < 48)
+        rk[threadIdx.x] = *reinterpret_cast<const uint4 *>(keys[m].w[threadIdx.x]);
+    __syncthreads();
+    if (threadIdx.x >= per) return;  // whole waves: per is a multiple of 64
+    const SpboxMsg d = msgs[m];
+    const uint64_t b = (uint64_t)(g - d.first_wg) * per + threadIdx.x;
+    if (b < d.nblocks)
+        blocks<1>(d.in, d.out, b, 0, reinterpret_cast<const uint8_t *>(table),
+                  (threadIdx.x % kCopies) * 4u, in_vgpr(kIndexMask), rk);
+}
+
 // Workgroups that fit on the current device at once, cached per device
 // (atomics: first calls from several threads may race; they all store the
 // same value).
@@ -203,6 +238,27 @@ hipError_t launch_spbox(const SpboxKeys &k, const uint8_t *in, uint8_t *out, siz
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL(tdes_spbox_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, in,
                        out, nblocks, per, k);
+    return hipGetLastError();
+}
+
+uint32_t spbox_multi_lanes(const uint64_t *nblocks, size_t n) {
+    const uint64_t cus = (uint64_t)resident_workgroups() / 2;
+    uint32_t per = 64;
+    for (; per < (uint32_t)kThreads; per *= 2) {
+        uint64_t wgs = 0;
+        for (size_t i = 0; i < n; i++) wgs += (nblocks[i] + per - 1) / per;
+        if (wgs <= cus) break;
+    }
+    return per;
+}
+
+hipError_t launch_spbox_multi(const SpboxMsg *d_msgs, uint32_t n, const SpboxKeys *d_keys,
+                              uint32_t per, uint32_t n_wg, hipStream_t stream) {
+    if (n == 0 || n > kSpboxMultiMax || n_wg == 0 || per == 0 || per % 64 != 0 ||
+        per > (uint32_t)kThreads)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tdes_spbox_multi_kernel, dim3(n_wg), dim3(kThreads), 0, stream, d_msgs, n,
+                       d_keys, per);
     return hipGetLastError();
 }
 

@@ -126,3 +126,30 @@ def test_budget_holds_under_load(env):
     assert (status == 0).all()
     assert st["peak_in_flight_bytes"] <= budget
     assert st["completed"] == len(reqs)
+
+
+# One burst per case, one slot: the whole burst is one batch.  Batches of 4 to
+# 64 requests and at most 4 MiB run as one table-kernel launch over the
+# requests, larger ones on the batched bitsliced path; every result is
+# compared with the oracle.
+TABLE_BANDS = ((0.70, 64, 1024), (0.30, 4096, 65536))
+
+
+@pytest.mark.parametrize("count,bands", [(4, TABLE_BANDS), (17, TABLE_BANDS), (64, TABLE_BANDS),
+                                         (65, TABLE_BANDS), (4, ((1.0, 1 << 20, 1 << 20),)),
+                                         (8, ((1.0, 1 << 20, 1 << 20),))])
+def test_burst_batches_equal_oracle(env, count, bands):
+    trace = W.serving_trace(W.SEED_BASE + 10 + count, rate=100000, duration_s=0.01, bands=bands)
+    assert len(trace["size"]) >= count
+    trace = {k: v[:count] for k, v in trace.items()}
+    torch, pool, arena, pad = env
+    reqs = S.make_requests(trace, pool.data_ptr(), pool.numel(), W.SEED_BASE + 11)
+    _say("serve burst", count, int(trace["size"].sum()), "bytes")
+    srv = _server(env, slots=1, max_batch_msgs=1024)
+    got, lat, status, st, batch_of = _run(env, srv, reqs, np.zeros(count), None)
+    srv.close()
+    assert (status == 0).all()
+    assert st["batches"] == 1, st["batches"]
+    for t in range(count):
+        want = oracle.tdes_ecb(trace["keys"][t], _pool_bytes(env, reqs[t]), bool(trace["dirs"][t]))
+        assert np.array_equal(got[t].cpu().numpy(), want), t

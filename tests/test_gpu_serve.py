@@ -153,3 +153,28 @@ def test_burst_batches_equal_oracle(env, count, bands):
     for t in range(count):
         want = oracle.tdes_ecb(trace["keys"][t], _pool_bytes(env, reqs[t]), bool(trace["dirs"][t]))
         assert np.array_equal(got[t].cpu().numpy(), want), t
+
+
+# Bursts of small requests with a few large ones (above 4 MiB in all, some
+# requests above the table kernel's one-pass size): the batched path.
+@pytest.mark.parametrize("big", [[(2, 5 << 19), (5, 5 << 19), (7, 5 << 19)],
+                                 [(3, 6 << 20)],
+                                 [(0, 2 << 20), (1, 2 << 20), (2, 2 << 20), (3, 2 << 20), (4, 2 << 20)]])
+def test_burst_with_large_requests(env, big):
+    count = 12
+    trace = W.serving_trace(W.SEED_BASE + 40 + len(big), rate=100000, duration_s=0.01,
+                            bands=TABLE_BANDS)
+    trace = {k: v[:count].copy() for k, v in trace.items()}
+    for i, nbytes in big:
+        trace["size"][i] = nbytes
+    torch, pool, arena, pad = env
+    reqs = S.make_requests(trace, pool.data_ptr(), pool.numel(), W.SEED_BASE + 12)
+    _say("serve burst with large", [b for _, b in big], int(trace["size"].sum()), "bytes")
+    srv = _server(env, slots=1, max_batch_msgs=1024)
+    got, lat, status, st, batch_of = _run(env, srv, reqs, np.zeros(count), None)
+    srv.close()
+    assert (status == 0).all()
+    assert st["batches"] == 1, st["batches"]
+    for t in range(count):
+        want = oracle.tdes_ecb(trace["keys"][t], _pool_bytes(env, reqs[t]), bool(trace["dirs"][t]))
+        assert np.array_equal(got[t].cpu().numpy(), want), t

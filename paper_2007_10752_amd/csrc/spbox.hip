@@ -178,7 +178,8 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_multi_kernel(const SpboxM
     const uint32_t g = blockIdx.x;
     const uint32_t l64 = threadIdx.x % 64;
     const bool le = l64 < n && msgs[l64].first_wg <= g;
-    const uint32_t m = (uint32_t)__popcll(__ballot(le)) - 1u;
+    const uint32_t k = (uint32_t)__popcll(__ballot(le));
+    const uint32_t m = k > 0 ? k - 1 : 0;  // (k is at least 1 when message 0 starts at 0)
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int c = threadIdx.x + j * kThreads;
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void tdes_spbox_multi_kernel(const SpboxM
     if (threadIdx.x >= per) return;  // whole waves: per is a multiple of 64
     const SpboxMsg d = msgs[m];
     const uint64_t b = (uint64_t)(g - d.first_wg) * per + threadIdx.x;
-    if (b < d.nblocks)
+    if (g >= d.first_wg && b < d.nblocks)
         blocks<1>(d.in, d.out, b, 0, reinterpret_cast<const uint8_t *>(table),
                   (threadIdx.x % kCopies) * 4u, in_vgpr(kIndexMask), rk);
 }

@@ -55,9 +55,9 @@ typedef enum { TDES_ENCRYPT = 0, TDES_DECRYPT = 1 } tdes_dir;
 /* Kernel selection for tdes_ecb_crypt. */
 typedef enum {
     TDES_KERNEL_AUTO = 0,     /* the library's choice: the table kernel up
-                                 to the bytes one wave of its resident
-                                 workgroups covers at one block per lane
-                                 (4 MiB on 256 CUs; lower latency), the
+                                 to 1.5 times the bytes one wave of its
+                                 resident workgroups covers at one block per
+                                 lane (6 MiB on 256 CUs; lower latency), the
                                  bitsliced kernel above (higher throughput) */
     TDES_KERNEL_BITSLICE = 1, /* 32 blocks per lane as bit planes; S-boxes
                                  as gate networks, E/P/IP/FP as renaming   */
@@ -65,9 +65,9 @@ typedef enum {
 } tdes_kernel;
 
 /* The kernel TDES_KERNEL_AUTO runs for nbytes on the current device:
- * TDES_KERNEL_SPBOX up to the table kernel's one-pass size (resident
- * workgroups x 1,024 lanes x 8 bytes: 4 MiB on 256 CUs), TDES_KERNEL_BITSLICE
- * above.  Returns a negative tdes_status (TDES_ERR_DEVICE) without a
+ * TDES_KERNEL_SPBOX up to 1.5 times the table kernel's one-pass size
+ * (resident workgroups x 1,024 lanes x 8 bytes: 6 MiB on 256 CUs),
+ * TDES_KERNEL_BITSLICE above.  Returns a negative tdes_status (TDES_ERR_DEVICE) without a
  * device. */
 int tdes_ecb_auto_kernel(size_t nbytes);
 
@@ -366,7 +366,7 @@ tdes_status tdes_batch_config_save(const char *path, const char *device, uint32_
 
 /* The key material a launch of `kernel` (TDES_KERNEL_BITSLICE or
  * TDES_KERNEL_SPBOX; AUTO gives the bitsliced kernel's, its choice above
- * the table kernel's one-pass size) would receive for
+ * 1.5 times the table kernel's one-pass size) would receive for
  * schedule ks and direction dir, copied to host memory `out` (cap bytes).
  * Returns the number of bytes written, or a negative tdes_status
  * (TDES_ERR_ARG for NULL pointers, bad enums or cap too small).  For

@@ -138,15 +138,15 @@ hipError_t batch_autotune(const tdes_msg *msgs, size_t n_msgs, const uint32_t *s
                           const TuneLane *lanes, int n_lanes, uint64_t out_bytes, int reps,
                           BatchConfig *best, float *best_us);
 // Bytes the table kernel covers with one block per lane in one wave of
-// resident workgroups on the current device (4 MiB on 256 CUs).  Up to this
-// size it has the lower latency: its lanes each run one block through the
-// rounds, while a bitsliced lane runs 32 (one launch of either kernel
-// measured 10-25 us against 33-35 us); above it the bitsliced kernel's
-// throughput wins.
+// resident workgroups on the current device (4 MiB on 256 CUs).  Up to 1.5
+// times this size it has the lower latency: its lanes each run one or two
+// blocks through the rounds, while a bitsliced lane runs 32 (one launch of
+// either kernel measured 8-29 us against 33-35 us); above it the bitsliced
+// kernel's throughput wins.
 size_t spbox_one_pass_bytes();
 
-// tdes_ecb_crypt's TDES_KERNEL_AUTO: the table kernel up to
-// spbox_one_pass_bytes(), the bitsliced kernel above (auto_kernel says which,
+// tdes_ecb_crypt's TDES_KERNEL_AUTO: the table kernel up to one and a half
+// times spbox_one_pass_bytes(), the bitsliced kernel above (auto_kernel says which,
 // as a tdes_kernel value).
 int auto_kernel(size_t nbytes);
 hipError_t launch_ecb_auto(const tdes_schedule &ks, int dir, const uint8_t *in, uint8_t *out,

@@ -143,17 +143,17 @@ def test_64mib_full(torch_dev, kernel, two_key):
     assert np.array_equal(rows, oracle.tdes_ecb(key, sample, decrypt=True))
 
 
-# The automatic kernel choice: the table kernel up to 4 MiB on a 256-CU
-# device (one block per lane, one wave of resident workgroups), the bitsliced
-# kernel above; sizes on both sides of that point, checked in full.
-AUTO_SIZES = [8, 32 << 10, (4 << 20) - 8, 4 << 20, (4 << 20) + 8, 8 << 20]
+# The automatic kernel choice: the table kernel up to 6 MiB on a 256-CU
+# device (one block per lane, 1.5 waves of resident workgroups), the
+# bitsliced kernel above; sizes on both sides of that point, checked in full.
+AUTO_SIZES = [8, 32 << 10, (4 << 20) + 8, (6 << 20) - 8, 6 << 20, (6 << 20) + 8, 8 << 20]
 
 
 def test_auto_kernel_query(torch_dev):
-    # the table kernel up to one pass of its resident workgroups (2 per CU,
+    # the table kernel up to 1.5 passes of its resident workgroups (2 per CU,
     # 1,024 lanes, one 8-byte block each), the bitsliced kernel above
     cus = torch_dev.cuda.get_device_properties(0).multi_processor_count
-    limit = 2 * cus * 1024 * 8
+    limit = 3 * cus * 1024 * 8
     assert T.auto_kernel(8) == "spbox"
     assert T.auto_kernel(limit) == "spbox"
     assert T.auto_kernel(limit + 8) == "bitslice"
